@@ -1,0 +1,319 @@
+"""Conventional, exact dual-matrix and BiP-PRISM EELS (FP64).
+
+Oracle (test infrastructure).  Implements
+
+* Alg. 1 (conventional transition-potential multislice): the ground truth.
+* Alg. 4 (exact dual-matrix map, PRISM factor f = 1): S1 over all aperture
+  beams, S2 over all detector beams, coupling on the crop window
+  (eq. coupling).
+* Alg. 5 (BiP-PRISM): S1 and S2 on lattice parents, windowed
+  reconstruction (eq. window-recon) in magnitude-preserving
+  (eq. magpreserve) or complex mode, then the same coupling.
+
+Conventions (readings of the paper, shared with the GPU path):
+* probe coefficients c_b = Psi(h_b) = 1/sqrt(G B) inside the aperture (no
+  aberrations), so the probe has unit norm (eq. probe);
+* illumination c_b(rho) = c_b exp(-2 pi i h_b.rho/N), rho on the raster
+  (u N_y/S_y, v N_x/S_x);
+* detector amplitudes use the unitary DFT;
+* de-tilt by the column's own carrier and re-tilt by the target beam's:
+  S1 carrier exp(+2 pi i h.r/N), S2 carrier exp(-2 pi i h.r/N);
+* sgn(0) = 0 in the magnitude-preserving mode;
+* outputs: MAP I(rho) (eq. map-sum), QEELS I(q_x, rho) resolving h_x and
+  summing h_y, BEAMS I(d, rho); summed over atoms in input order and over
+  channels in order.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import multislice as ms
+from . import physics
+from .sibson import Partition
+
+RECON_MAGNITUDE = 0
+RECON_COMPLEX = 1
+OUT_MAP, OUT_QEELS, OUT_BEAMS = 0, 1, 2
+
+
+# ------------------------------------------------------------------ geometry
+def window_pixels(cfg, W, origin):
+    """Absolute (y, x) pixel indices of a W x W window at origin (mod N)."""
+    y = (origin[0] + np.arange(W)) % cfg.ny
+    x = (origin[1] + np.arange(W)) % cfg.nx
+    return y, x
+
+
+def carrier(cfg, h, y, x, sign):
+    """exp(sign 2 pi i (h_y y/N_y + h_x x/N_x)) on window pixels [.., W, W]."""
+    h = np.atleast_2d(h)
+    ph = (h[:, 0, None, None] * y[None, :, None]) / cfg.ny + \
+         (h[:, 1, None, None] * x[None, None, :]) / cfg.nx
+    return np.exp(sign * 2j * math.pi * ph)
+
+
+def scan_positions(cfg):
+    """Raster positions (rho_y, rho_x) in pixels, p = u S_x + v."""
+    sy, sx = cfg.scan
+    u, v = np.meshgrid(np.arange(sy), np.arange(sx), indexing="ij")
+    return np.stack([u.ravel() * cfg.ny / sy, v.ravel() * cfg.nx / sx], axis=1)
+
+
+def illumination(cfg, beams):
+    """c_b(rho) [P, B] = c_b exp(-2 pi i (h_y u / S_y + h_x v / S_x))."""
+    sy, sx = cfg.scan
+    G = cfg.ny * cfg.nx
+    cb = 1.0 / math.sqrt(G * len(beams))
+    u, v = np.meshgrid(np.arange(sy), np.arange(sx), indexing="ij")
+    u = u.ravel()[:, None]
+    v = v.ravel()[:, None]
+    ph = (beams[None, :, 0] * u) / sy + (beams[None, :, 1] * v) / sx
+    return cb * np.exp(-2j * math.pi * ph)
+
+
+def qeels_bins(cfg):
+    """Number of q_x bins and the bin of each detector beam (h_x + floor(r))."""
+    lam = physics.wavelength(cfg.energy_ev)
+    r = cfg.theta / lam * cfg.lx
+    half = int(math.floor(r + 1e-12))
+    return 2 * half + 1, half
+
+
+def reduce_output(cfg, I_dp, det, mode):
+    """Reduce per-beam intensities I[d, rho] to the requested output."""
+    if mode == OUT_BEAMS:
+        return I_dp.T.copy()                     # [P, n_det]
+    if mode == OUT_MAP:
+        return I_dp.sum(axis=0)                  # [P]
+    nq, half = qeels_bins(cfg)
+    out = np.zeros((I_dp.shape[1], nq))
+    np.add.at(out.T, det[:, 1] + half, I_dp)
+    return out                                   # [P, n_q]
+
+
+# -------------------------------------------------------------- contraction
+def contract_probe_order(S1w, S2w, H, C):
+    """Per-beam intensity of one atom, probe order.
+
+    S1w [B, W, W], S2w [n_det, W, W], H [n_ch, W, W], C [P, B].
+    psi(r, rho) = sum_b S1^b(r) c_b(rho); a_d = sum_r S2^d(r) H_n(r) psi(r, rho);
+    returns sum_n |a_d|^2 as [n_det, P]."""
+    B = S1w.shape[0]
+    K = S1w.shape[1] * S1w.shape[2]
+    psi = S1w.reshape(B, K).T @ C.T               # [K, P]
+    S2 = S2w.reshape(S2w.shape[0], K)
+    I = np.zeros((S2.shape[0], C.shape[0]))
+    for n in range(H.shape[0]):
+        a = S2 @ (H[n].reshape(K, 1) * psi)      # [n_det, P]
+        I += a.real ** 2 + a.imag ** 2
+    return I
+
+
+def contract_m_order(S1w, S2w, H, C):
+    """Same quantity via the coupling matrix M_{d,b} (Alg. 4 order)."""
+    B = S1w.shape[0]
+    K = S1w.shape[1] * S1w.shape[2]
+    S1 = S1w.reshape(B, K)
+    S2 = S2w.reshape(S2w.shape[0], K)
+    I = np.zeros((S2.shape[0], C.shape[0]))
+    for n in range(H.shape[0]):
+        M = (S2 * H[n].reshape(1, K)) @ S1.T     # [n_det, B]
+        a = M @ C.T
+        I += a.real ** 2 + a.imag ** 2
+    return I
+
+
+# ---------------------------------------------------------- reconstruction
+def reconstruct(cfg, win, parents, Wmat, beams, y, x, side, mode=RECON_MAGNITUDE):
+    """Windowed reconstruction of all beams of one matrix (eq. window-recon).
+
+    win [Bp, W, W]: parent columns cropped to the window.  side = 1 for S1
+    (carrier +), 2 for S2 (carrier -).  Magnitude mode follows eq.
+    magpreserve: (sum_p w |D_p|) * sgn(sum_p w D_p), then re-tilt."""
+    s = +1 if side == 1 else -1
+    D = win * carrier(cfg, parents, y, x, -s)         # de-tilt
+    Wd = Wmat.tocsr()
+    Bp = D.shape[0]
+    K = D.shape[1] * D.shape[2]
+    Df = D.reshape(Bp, K)
+    z = Wd @ Df                                        # [n_beams, K]
+    if mode == RECON_COMPLEX:
+        rec = z
+    else:
+        m = Wd @ np.abs(Df)
+        az = np.abs(z)
+        sgn = np.where(az > 0, z / np.where(az > 0, az, 1.0), 0.0)
+        rec = m * sgn
+    rec = rec.reshape(-1, D.shape[1], D.shape[2])
+    return rec * carrier(cfg, beams, y, x, +s)        # re-tilt
+
+
+# ---------------------------------------------------------------- problem
+class Problem:
+    """Everything the three algorithms share for one specimen."""
+
+    def __init__(self, cfg, V, tau, win_size, win_origin, H, H_off, n_ch):
+        self.cfg = cfg
+        self.V = np.asarray(V)
+        self.T = physics.transmissions(cfg, self.V)
+        self.P = physics.propagator(cfg)
+        self.beams = physics.aperture_beams(cfg)
+        self.det = physics.detector_beams(cfg)
+        self.tau = np.asarray(tau, dtype=np.float64)
+        self.win_size = np.asarray(win_size)
+        self.win_origin = np.asarray(win_origin)
+        self.n_ch = n_ch
+        self.H_flat = np.asarray(H)
+        self.H_off = np.asarray(H_off)
+        self.planes = np.array([physics.slice_of(cfg, z) for z in self.tau[:, 2]], dtype=np.int64)
+
+    @classmethod
+    def from_specimen(cls, sp):
+        return cls(sp.cfg, sp.V, sp.tau, sp.win_size, sp.win_origin, sp.H, sp.H_off, sp.n_ch)
+
+    def H_atom(self, a):
+        W = int(self.win_size[a])
+        return self.H_flat[self.H_off[a]:self.H_off[a + 1]].reshape(self.n_ch, W, W).astype(np.complex128)
+
+    def window(self, a):
+        return window_pixels(self.cfg, int(self.win_size[a]), self.win_origin[a])
+
+    def crop(self, cols, a):
+        y, x = self.window(a)
+        return cols[:, y[:, None], x[None, :]]
+
+
+def _atoms(prob, atoms):
+    return list(range(len(prob.tau))) if atoms is None else list(atoms)
+
+
+# -------------------------------------------------------------- Algorithm 1
+def conventional(prob: Problem, mode=OUT_MAP, atoms=None, scans=None):
+    """Alg. 1: per scan position, form the probe, multislice it, and at each
+    slice containing ionized atoms spawn H_n psi and propagate it to the exit.
+    H is the window-restricted transition potential (zero off the window)."""
+    cfg = prob.cfg
+    atoms = _atoms(prob, atoms)
+    C = illumination(cfg, prob.beams)                 # [P, B]
+    Pn = C.shape[0]
+    scans = range(Pn) if scans is None else scans
+    S0 = ms.initial_s1(cfg, prob.beams)               # plane waves
+    G = cfg.ny * cfg.nx
+    I_dp = np.zeros((len(prob.det), Pn))
+    by_plane = {}
+    for a in atoms:
+        by_plane.setdefault(int(prob.planes[a]), []).append(a)
+    for p in scans:
+        psi = np.tensordot(C[p], S0, axes=(0, 0))     # eq. probe
+        for i in range(cfg.nz):
+            for a in by_plane.get(i, []):
+                y, x = prob.window(a)
+                Ha = prob.H_atom(a)
+                for n in range(prob.n_ch):
+                    phi = np.zeros_like(psi)
+                    phi[y[:, None], x[None, :]] = Ha[n] * psi[y[:, None], x[None, :]]
+                    phi = ms.exit_operator(phi, prob.T, prob.P, i)
+                    F = ms.fft2(phi) / math.sqrt(G)
+                    amp = F[prob.det[:, 0] % cfg.ny, prob.det[:, 1] % cfg.nx]
+                    I_dp[:, p] += amp.real ** 2 + amp.imag ** 2
+            psi = ms.step(psi, prob.T[i], prob.P)
+    return reduce_output(cfg, I_dp, prob.det, mode)
+
+
+# -------------------------------------------------------------- Algorithm 4
+def exact_dual(prob: Problem, mode=OUT_MAP, atoms=None, order="probe"):
+    """Alg. 4 with f = 1: exact S1 (all aperture beams) and S2 (all detector
+    beams) at each ionization plane; coupling on the crop window."""
+    cfg = prob.cfg
+    atoms = _atoms(prob, atoms)
+    planes = sorted(set(int(prob.planes[a]) for a in atoms))
+    S1 = ms.s1_at_planes(cfg, prob.beams, prob.T, prob.P, planes)
+    S2 = ms.s2_at_planes(cfg, prob.det, prob.T, prob.P, planes)
+    C = illumination(cfg, prob.beams)
+    contract = contract_probe_order if order == "probe" else contract_m_order
+    I_dp = np.zeros((len(prob.det), C.shape[0]))
+    for a in atoms:
+        i = int(prob.planes[a])
+        I_dp += contract(prob.crop(S1[i], a), prob.crop(S2[i], a), prob.H_atom(a), C)
+    return reduce_output(cfg, I_dp, prob.det, mode)
+
+
+# -------------------------------------------------------------- Algorithm 5
+class BiP:
+    """Alg. 5: parents, weights, parent sweeps, windowed reconstruction."""
+
+    def __init__(self, prob: Problem, recon_mode=RECON_MAGNITUDE):
+        self.prob = prob
+        cfg = prob.cfg
+        self.part1 = Partition(prob.beams, cfg.partition)
+        self.part2 = Partition(prob.det, cfg.partition)
+        self.recon_mode = recon_mode
+
+    def parent_windows(self, atoms):
+        """{atom: (S1 parent windows [Bp1, W, W], S2 parent windows [Bp2, W, W])}."""
+        prob = self.prob
+        cfg = prob.cfg
+        planes = sorted(set(int(prob.planes[a]) for a in atoms))
+        out = {}
+        # propagate parents plane by plane, cropping as we go (memory-light)
+        S1 = ms.s1_at_planes(cfg, self.part1.parents, prob.T, prob.P, planes)
+        for a in atoms:
+            out[a] = [prob.crop(S1[int(prob.planes[a])], a), None]
+        del S1
+        S2 = ms.s2_at_planes(cfg, self.part2.parents, prob.T, prob.P, planes)
+        for a in atoms:
+            out[a][1] = prob.crop(S2[int(prob.planes[a])], a)
+        return out
+
+    def reconstructed(self, a, pw):
+        """(S1~ [B, W, W], S2~ [n_det, W, W]) on the window of atom a."""
+        prob = self.prob
+        y, x = prob.window(a)
+        s1 = reconstruct(prob.cfg, pw[0], self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+                         self.recon_mode)
+        s2 = reconstruct(prob.cfg, pw[1], self.part2.parents, self.part2.W, prob.det, y, x, 2,
+                         self.recon_mode)
+        return s1, s2
+
+    def run(self, mode=OUT_MAP, atoms=None, order="probe", scans=None, per_atom=False):
+        prob = self.prob
+        atoms = _atoms(prob, atoms)
+        pw = self.parent_windows(atoms)
+        C = illumination(prob.cfg, prob.beams)
+        if scans is not None:
+            C = C[np.asarray(scans)]
+        contract = contract_probe_order if order == "probe" else contract_m_order
+        I_dp = np.zeros((len(prob.det), C.shape[0]))
+        parts = {}
+        for a in atoms:
+            s1, s2 = self.reconstructed(a, pw[a])
+            Ia = contract(s1, s2, prob.H_atom(a), C)
+            if per_atom:
+                parts[a] = Ia
+            I_dp += Ia
+        out = reduce_output(prob.cfg, I_dp, prob.det, mode)
+        return (out, parts) if per_atom else out
+
+
+# ------------------------------------------------------------- diagnostics
+def on_atom_error(prob: Problem, bip: BiP, a: int):
+    """eps_on-atom = ||psi^p - psi||_Omega / ||psi||_Omega (eq. onatom),
+    aggregated over all scan positions."""
+    cfg = prob.cfg
+    i = int(prob.planes[a])
+    exact = prob.crop(ms.s1_at_planes(cfg, prob.beams, prob.T, prob.P, [i])[i], a)
+    pw = bip.parent_windows([a])[a]
+    rec, _ = bip.reconstructed(a, pw)
+    C = illumination(cfg, prob.beams)
+    K = exact.shape[1] * exact.shape[2]
+    psi = exact.reshape(-1, K).T @ C.T
+    psip = rec.reshape(-1, K).T @ C.T
+    return float(np.linalg.norm(psip - psi) / np.linalg.norm(psi))
+
+
+def rel_l2(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
