@@ -1,0 +1,184 @@
+/*
+ * bip.h -- C ABI of the BiP-PRISM core-loss STEM-EELS hot path on MI355X.
+ *
+ * The library computes the bi-partitioned PRISM-EELS map of Pelz,
+ * "The BiP-PRISM algorithm for fast and scalable core-loss STEM-EELS
+ * simulations" (Alg. 5, section "Bi-partitioned PRISM-EELS"):
+ *   (a) multislice of the parent beams of the probe-forming matrix S1
+ *       (eq. smatrix-advance) and of the detector matrix S2 by transpose
+ *       multislice (eq. s2), with the parent columns cropped to each ionized
+ *       atom's window as the sweep passes its plane;
+ *   (b) Sibson natural-neighbour reconstruction of S1 and S2 on the window
+ *       (eq. nnw, eq. window-recon, magnitude preserving eq. magpreserve);
+ *   (c) the contraction of illumination coefficients x S1 x H_n x S2 into
+ *       intensities (eq. coupling, eq. map-sum, section "Output modes").
+ *
+ * Conventions shared by every entry point
+ *   - Units: Angstrom, eV, rad.  V is the projected potential in V*A.
+ *   - Grid: corner-origin DFT grid, pixel (y, x), x fastest; beam index
+ *     h = (h_y, h_x) signed in [-N/2, N/2); q = h / L.
+ *   - Complex arrays are interleaved float pairs (re, im) ("complex64").
+ *   - Every pointer is owned by the caller and must stay valid until the
+ *     work queued on `stream` has finished.  `stream` is a hipStream_t
+ *     (NULL = the default stream).  Device pointers are marked "device",
+ *     host pointers "host".
+ *   - All calls return 0 (BIP_OK) or a negative BIP_E* code, never abort;
+ *     bip_last_error() gives a message.  Argument validation happens on the
+ *     host before anything is launched.  After an error the plan stays
+ *     valid and the outputs are undefined.
+ *   - A plan is not thread safe; different plans are independent.
+ *   - Results are bitwise reproducible for identical inputs (no atomics in
+ *     any reduction).
+ */
+#ifndef BIP_H
+#define BIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BIP_OK = 0,
+  BIP_EINVAL = -1,       /* bad shape, range, or non power-of-two grid        */
+  BIP_EUNSUPPORTED = -2, /* valid request outside what the library implements */
+  BIP_ENOMEM = -3,       /* device allocation failed                          */
+  BIP_EHIP = -4,         /* a HIP runtime call failed                         */
+  BIP_ESTATE = -5        /* call out of order (e.g. signal before build)      */
+};
+
+enum { BIP_RECON_MAGNITUDE = 0, BIP_RECON_COMPLEX = 1 };
+enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2 };
+enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2 };
+
+typedef struct bip_grid {
+  int32_t ny, nx, nz;   /* pixels (powers of two, 64..1024) and slice count */
+  double ly, lx, dz;    /* field of view and slice thickness (A)            */
+} bip_grid;
+
+typedef struct bip_optics {
+  double energy_ev;     /* beam energy                                       */
+  double alpha_rad;     /* probe convergence semi-angle: aperture |q| <= alpha/lambda */
+  double theta_rad;     /* collection semi-angle: detector |q| <= theta/lambda        */
+  int32_t partition;    /* parent lattice factor s >= 1 (s = 1: exact PRISM)         */
+  int32_t recon_mode;   /* BIP_RECON_MAGNITUDE (eq. magpreserve) or BIP_RECON_COMPLEX */
+} bip_optics;
+
+typedef struct bip_plan bip_plan;
+
+/*
+ * bip_plan_create -- geometry and workspace for one specimen.
+ * Passage: Alg. 5 "Require" (aperture, detector semi-angle, crop windows,
+ * parent counts) and the build step of Alg. 3 (parent set, cached
+ * natural-neighbour weights, eq. nnw).
+ *   grid, optics   host structs (copied).
+ *   n_atoms        number of ionized atoms (>= 1).
+ *   tau_xyz        host f64 [n_atoms][3] positions (x, y, z) in A; the atom
+ *                  ionizes at the entrance of slice floor(z / dz) (clamped).
+ *   win_size       host i32 [n_atoms] window side W (4 <= W <= min(ny, nx),
+ *                  W % 4 == 0).
+ *   win_origin     host i32 [n_atoms][2] window origin (oy, ox) in pixels,
+ *                  taken mod N; the window wraps periodically.
+ * Computes on the GPU, in FP64: aperture and detector beams, the Sibson
+ * weights of every beam on the parent lattice s Z^2, and the propagator
+ * phase table.  Parents are the lattice points with a weight > 1e-12 for
+ * some beam.  Allocates all device workspace of the plan (parent columns,
+ * window stacks).  Synchronizes `stream` once (to size the parent sets).
+ * Errors: BIP_EINVAL (shapes/ranges), BIP_EUNSUPPORTED (aperture or detector
+ * beyond Nyquist, parents outside the grid), BIP_ENOMEM, BIP_EHIP.
+ */
+int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_atoms,
+                    const double* tau_xyz, const int32_t* win_size, const int32_t* win_origin,
+                    void* stream, bip_plan** out);
+
+/*
+ * bip_build_smatrix -- step (a): parent sweeps and window gathers.
+ * Passage: eq. smatrix-advance (S1 advance), eq. s2 (S2 by transpose
+ * multislice), eq. window-recon (cropped parent columns), Alg. 5 steps 1-4.
+ *   V  device f32 [nz][ny][nx] projected potential (V*A); read only.
+ * S1 parents start as unit plane waves exp(+2 pi i h_p.r/N) and advance
+ * psi <- F^-1[P F[T_j psi]], T_j = exp(i sigma V_j); at each atom's plane
+ * (before T_i) the W x W window is cropped and de-tilted by
+ * exp(-2 pi i h_p.r/N).  S2 parents start as G^-1/2 exp(-2 pi i h_p.r/N) and
+ * step v <- T_j F^-1[P F[v]] from slice nz-1 down; at each atom's plane
+ * (after T_i) the window is cropped and de-tilted by exp(+2 pi i h_p.r/N).
+ * Asynchronous on `stream`.  Errors: BIP_EINVAL, BIP_EHIP.
+ */
+int bip_build_smatrix(bip_plan* plan, const float* V, void* stream);
+
+/*
+ * bip_reconstruct_local -- step (b), materialized for one atom.
+ * Passage: eq. window-recon with eq. magpreserve (or the complex sum).
+ *   atom     index in [0, n_atoms).
+ *   s1_out   device complex64 [B][W][W]: S1~^b on the window (aperture beam
+ *            order of bip_query BIP_Q_BEAMS), or NULL.
+ *   s2_out   device complex64 [n_det][W][W]: S2~^d (BIP_Q_DETECTOR order),
+ *            or NULL.
+ * Requires a prior bip_build_smatrix (else BIP_ESTATE).
+ */
+int bip_reconstruct_local(bip_plan* plan, int32_t atom, float* s1_out, float* s2_out,
+                          void* stream);
+
+/*
+ * bip_eels_signal -- steps (b) + (c): core-loss intensities.
+ * Passage: eq. coupling evaluated in probe order (psi = sum_b c_b(rho) S1~^b
+ * on the window, U_n = H_n psi, a_d = sum_r S2~^d U_n), eq. map-sum and the
+ * output reductions of section "Output modes".
+ *   n_ch         channels per atom (>= 1).
+ *   H            device complex64, ragged [atom][n_ch][W_a][W_a]: H_n0 on
+ *                each atom's window (zero outside it).
+ *   H_off        host i64 [n_atoms + 1] element offsets of each atom in H.
+ *   atom_subset  host i32 [n_subset] atoms to include (NULL = all atoms);
+ *                contributions are summed in the listed order.
+ *   scan_sy/sx   raster S_y x S_x over the whole cell: rho_(u,v) =
+ *                (u N_y/S_y, v N_x/S_x) pixels; output row p = u S_x + v.
+ *   out_mode     BIP_OUT_MAP: out f32 [P]; BIP_OUT_QEELS: f32 [P][n_q]
+ *                (h_x resolved, bin h_x + floor(theta L_x / lambda));
+ *                BIP_OUT_BEAMS: f32 [P][n_det] (detector order of bip_query).
+ *   precision    BIP_PREC_FP32 (FP32 MFMA), BIP_PREC_SPLIT_BF16 (hi+lo
+ *                bf16 products, FP32 accumulate) or BIP_PREC_BF16.
+ *   out          device f32, overwritten.
+ * Probe coefficients are c_b = 1/sqrt(G B) (unit-norm probe, no aberrations).
+ * Errors: BIP_EINVAL, BIP_ESTATE (no build), BIP_ENOMEM, BIP_EHIP.
+ */
+int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t* H_off,
+                    const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
+                    int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
+                    void* stream);
+
+/*
+ * bip_parent_windows -- the cropped, de-tilted parent windows gathered by
+ * bip_build_smatrix for one atom (step a8), for inspection and parity tests.
+ *   which   1 (S1 parents) or 2 (S2 parents).
+ *   out     device complex64 [Bp][W][W]; D_p(r) = S_p(r) exp(-/+ 2 pi i h_p.r/N).
+ */
+int bip_parent_windows(bip_plan* plan, int32_t atom, int32_t which, float* out, void* stream);
+
+enum {
+  BIP_Q_COUNTS = 0,   /* i64[8]: B, n_det, Bp1, Bp2, n_q, n_atoms, nnz1, nnz2 */
+  BIP_Q_BEAMS = 1,    /* i32 [B][2]     aperture beams (h_y, h_x), sorted     */
+  BIP_Q_DETECTOR = 2, /* i32 [n_det][2] detector beams, sorted                */
+  BIP_Q_PARENTS1 = 3, /* i32 [Bp1][2]   S1 parents, sorted                    */
+  BIP_Q_PARENTS2 = 4, /* i32 [Bp2][2]   S2 parents, sorted                    */
+  BIP_Q_PLANES = 5,   /* i32 [n_atoms]  ionization plane of each atom         */
+  BIP_Q_WEIGHTS1 = 6, /* CSR of w(1): i32 rowptr[B+1], i32 col[nnz1], f64 w[nnz1] packed
+                         back to back in that order (host buffer)             */
+  BIP_Q_WEIGHTS2 = 7, /* same for the detector weights w(2)                   */
+  BIP_Q_SCALARS = 8   /* f64[4]: lambda (A), sigma (rad/(V A)), 0, 0          */
+};
+
+/* bip_query -- copy plan metadata into the host buffer `out`. */
+int bip_query(const bip_plan* plan, int32_t what, void* out);
+
+/* bip_plan_destroy -- synchronizes and frees every device buffer of the plan. */
+void bip_plan_destroy(bip_plan* plan);
+
+/* bip_last_error -- message of the last failure on this thread ("" if none). */
+const char* bip_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIP_H */

@@ -1,0 +1,172 @@
+"""Thin Python binding of libbip.so (include/bip.h): argument marshalling only.
+
+Device buffers are torch tensors on the current HIP device; the stream is
+torch's current stream.  Every computation runs in the HIP library; if the
+library is missing this module raises at import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbip.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2607_00756_amd.build`")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
+RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
+OUT_MAP, OUT_QEELS, OUT_BEAMS = 0, 1, 2
+PREC_FP32, PREC_SPLIT_BF16, PREC_BF16 = 0, 1, 2
+Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
+    Q_SCALARS = range(9)
+
+EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
+           "bip_parent_windows", "bip_query", "bip_plan_destroy", "bip_last_error"]
+
+
+class BipGrid(ctypes.Structure):
+    _fields_ = [("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ly", ctypes.c_double), ("lx", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class BipOptics(ctypes.Structure):
+    _fields_ = [("energy_ev", ctypes.c_double), ("alpha_rad", ctypes.c_double),
+                ("theta_rad", ctypes.c_double), ("partition", ctypes.c_int32),
+                ("recon_mode", ctypes.c_int32)]
+
+
+_p = ctypes.c_void_p
+_lib.bip_plan_create.argtypes = [ctypes.POINTER(BipGrid), ctypes.POINTER(BipOptics), ctypes.c_int32,
+                                 _p, _p, _p, _p, ctypes.POINTER(_p)]
+_lib.bip_build_smatrix.argtypes = [_p, _p, _p]
+_lib.bip_reconstruct_local.argtypes = [_p, ctypes.c_int32, _p, _p, _p]
+_lib.bip_eels_signal.argtypes = [_p, ctypes.c_int32, _p, _p, _p, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p]
+_lib.bip_parent_windows.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p]
+_lib.bip_query.argtypes = [_p, ctypes.c_int32, _p]
+_lib.bip_plan_destroy.argtypes = [_p]
+_lib.bip_plan_destroy.restype = None
+_lib.bip_last_error.restype = ctypes.c_char_p
+for _f in EXPORTS[:6]:
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class BipError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bip error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise BipError(rc, _lib.bip_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Plan:
+    """A bip_plan: geometry, parents, Sibson weights and device workspace."""
+
+    def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
+                 win_size, win_origin, recon_mode=RECON_MAGNITUDE, stream=None):
+        self._h = _p()
+        grid = BipGrid(ny, nx, nz, ly, lx, dz)
+        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode)
+        tau, tp = _host(tau_xyz, np.float64)
+        ws, wp = _host(win_size, np.int32)
+        wo, op = _host(win_origin, np.int32)
+        _check(_lib.bip_plan_create(ctypes.byref(grid), ctypes.byref(opt), int(tau.shape[0]), tp,
+                                    wp, op, _stream(stream), ctypes.byref(self._h)))
+        self.ny, self.nx, self.nz = ny, nx, nz
+        self.win_size = ws.copy()
+        c = self.query(Q_COUNTS)
+        self.B, self.ndet, self.Bp1, self.Bp2, self.nq, self.n_atoms, self.nnz1, self.nnz2 = \
+            (int(v) for v in c)
+
+    @classmethod
+    def from_config(cls, cfg, tau, win_size, win_origin, **kw):
+        return cls(cfg.ny, cfg.nx, cfg.nz, cfg.ly, cfg.lx, cfg.dz, cfg.energy_ev, cfg.alpha,
+                   cfg.theta, cfg.partition, tau, win_size, win_origin, **kw)
+
+    def close(self):
+        if self._h:
+            _lib.bip_plan_destroy(self._h)
+            self._h = _p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- entry points
+    def build_smatrix(self, V, stream=None):
+        """V: float32 device tensor [nz, ny, nx]."""
+        assert V.is_contiguous() and V.dtype.itemsize == 4
+        _check(_lib.bip_build_smatrix(self._h, _ptr(V), _stream(stream)))
+
+    def reconstruct_local(self, atom, s1_out=None, s2_out=None, stream=None):
+        """s1_out: complex64 [B, W, W]; s2_out: complex64 [n_det, W, W] (device)."""
+        _check(_lib.bip_reconstruct_local(self._h, atom, _ptr(s1_out), _ptr(s2_out), _stream(stream)))
+
+    def parent_windows(self, atom, which, out, stream=None):
+        _check(_lib.bip_parent_windows(self._h, atom, which, _ptr(out), _stream(stream)))
+
+    def eels_signal(self, n_ch, H, H_off, scan, out_mode, precision, out, atom_subset=None,
+                    stream=None):
+        """H: complex64 device [ragged]; H_off: host int64 [n_atoms+1]."""
+        offs, op = _host(H_off, np.int64)
+        if atom_subset is None:
+            sp, ns = ctypes.c_void_p(0), 0
+        else:
+            sub, sp = _host(atom_subset, np.int32)
+            ns = int(sub.size)
+        _check(_lib.bip_eels_signal(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]),
+                                    int(scan[1]), int(out_mode), int(precision), _ptr(out),
+                                    _stream(stream)))
+
+    # ------------------------------------------------------------------- query
+    def query(self, what):
+        if what == Q_COUNTS:
+            buf = np.zeros(8, np.int64)
+        elif what in (Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2):
+            n = {Q_BEAMS: self.B, Q_DETECTOR: self.ndet, Q_PARENTS1: self.Bp1,
+                 Q_PARENTS2: self.Bp2}[what]
+            buf = np.zeros((n, 2), np.int32)
+        elif what == Q_PLANES:
+            buf = np.zeros(self.n_atoms, np.int32)
+        elif what in (Q_WEIGHTS1, Q_WEIGHTS2):
+            nb, nnz = (self.B, self.nnz1) if what == Q_WEIGHTS1 else (self.ndet, self.nnz2)
+            raw = np.zeros(4 * (nb + 1) + 4 * nnz + 8 * nnz + 8, np.uint8)
+            _check(_lib.bip_query(self._h, what, raw.ctypes.data_as(ctypes.c_void_p)))
+            rp = raw[:4 * (nb + 1)].view(np.int32)
+            col = raw[4 * (nb + 1):4 * (nb + 1) + 4 * nnz].view(np.int32)
+            w = raw[4 * (nb + 1) + 4 * nnz:4 * (nb + 1) + 12 * nnz].view(np.float64)
+            return rp.copy(), col.copy(), w.copy()
+        elif what == Q_SCALARS:
+            buf = np.zeros(4, np.float64)
+        else:
+            raise ValueError(what)
+        _check(_lib.bip_query(self._h, what, buf.ctypes.data_as(ctypes.c_void_p)))
+        return buf
+
+
+def library_path() -> str:
+    return _LIB_PATH

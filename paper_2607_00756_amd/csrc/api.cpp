@@ -1,0 +1,647 @@
+// C ABI of the BiP-PRISM hot path: validation, plan geometry, and the
+// stream-ordered orchestration of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bip_internal.h"
+
+namespace bip {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return BIP_EHIP;
+}
+
+namespace {
+
+constexpr double kH = 6.62607015e-34, kE = 1.602176634e-19, kC = 299792458.0,
+                 kM = 9.1093837015e-31, kPi = 3.14159265358979323846;
+
+// relativistic wavelength (A) and interaction constant (rad / (V A))
+double wavelength(double ev) {
+  const double e = kE * ev, mc2 = kM * kC * kC;
+  return kH / std::sqrt(2.0 * kM * e * (1.0 + e / (2.0 * mc2))) * 1e10;
+}
+double interaction(double ev) {
+  const double mc2 = kM * kC * kC / kE;
+  return 2.0 * kPi / (wavelength(ev) * ev) * (mc2 + ev) / (2.0 * mc2 + ev);
+}
+
+bool pow2_in_range(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
+int64_t roundup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+int err(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+#define HIPCHK(expr, what)                         \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+int dalloc(bip_plan* p, T** out, size_t count) {
+  *out = nullptr;
+  if (count == 0) return BIP_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return err(BIP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  p->allocations.push_back(ptr);
+  *out = (T*)ptr;
+  return BIP_OK;
+}
+
+template <typename T>
+int upload(bip_plan* p, T** out, const std::vector<T>& v, hipStream_t s) {
+  int rc = dalloc(p, out, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  return BIP_OK;
+}
+
+// beams h (sorted by (h_y, h_x)) with (h_y/L_y)^2 + (h_x/L_x)^2 <= qmax^2
+std::vector<int32_t> beams_within(int ny, int nx, double ly, double lx, double qmax) {
+  std::vector<int32_t> out;
+  for (int hy = -ny / 2; hy < ny / 2; ++hy)
+    for (int hx = -nx / 2; hx < nx / 2; ++hx) {
+      const double qy = hy / ly, qx = hx / lx;
+      if (qy * qy + qx * qx <= qmax * qmax) {
+        out.push_back(hy);
+        out.push_back(hx);
+      }
+    }
+  return out;
+}
+
+// Run the FP64 Sibson kernel on `query` and build the parent set + CSR.
+int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector<int32_t>& parents,
+              std::vector<int32_t>& rowptr, std::vector<int32_t>& col, std::vector<double>& w,
+              hipStream_t st) {
+  const int nq = (int)query.size() / 2;
+  int2* dq = nullptr;
+  int2* dslot = nullptr;
+  double* dw = nullptr;
+  void* tmp[3] = {nullptr, nullptr, nullptr};
+  HIPCHK(hipMalloc(&tmp[0], std::max<size_t>(1, query.size() * sizeof(int32_t))), "sibson alloc");
+  HIPCHK(hipMalloc(&tmp[1], std::max<size_t>(1, (size_t)nq * 16 * sizeof(int2))), "sibson alloc");
+  HIPCHK(hipMalloc(&tmp[2], std::max<size_t>(1, (size_t)nq * 16 * sizeof(double))), "sibson alloc");
+  dq = (int2*)tmp[0];
+  dslot = (int2*)tmp[1];
+  dw = (double*)tmp[2];
+  std::vector<int2> slot((size_t)nq * 16);
+  std::vector<double> sw((size_t)nq * 16);
+  hipError_t e = hipMemcpyAsync(dq, query.data(), query.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_sibson(dq, nq, s, dslot, dw, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(slot.data(), dslot, slot.size() * sizeof(int2), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sw.data(), dw, sw.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (void* t : tmp) (void)hipFree(t);
+  if (e != hipSuccess) return hip_fail(e, "sibson weights");
+  const double eps = 1e-12;
+  std::map<std::pair<int, int>, int> index;
+  for (size_t i = 0; i < slot.size(); ++i)
+    if (sw[i] > eps) index[{slot[i].x, slot[i].y}] = 0;
+  parents.clear();
+  int k = 0;
+  for (auto& kv : index) {
+    kv.second = k++;
+    parents.push_back(kv.first.first);
+    parents.push_back(kv.first.second);
+  }
+  rowptr.assign(nq + 1, 0);
+  col.clear();
+  w.clear();
+  for (int q = 0; q < nq; ++q) {
+    // order the nonzeros of a row by parent index
+    std::vector<std::pair<int, double>> row;
+    for (int j = 0; j < 16; ++j) {
+      const size_t i = (size_t)q * 16 + j;
+      if (sw[i] > eps) row.push_back({index[{slot[i].x, slot[i].y}], sw[i]});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto& rw : row) {
+      col.push_back(rw.first);
+      w.push_back(rw.second);
+    }
+    rowptr[q + 1] = (int32_t)col.size();
+  }
+  return BIP_OK;
+}
+
+struct Workspace {
+  char* base = nullptr;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    void* p = base + used;
+    used += roundup((int64_t)bytes, 256);
+    return p;
+  }
+};
+
+int ensure_work(bip_plan* p, size_t bytes) {
+  if (p->work_bytes >= bytes) return BIP_OK;
+  if (p->d_work) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_work);
+    p->d_work = nullptr;
+    p->work_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&p->d_work, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_work = nullptr;
+    return err(BIP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes");
+  }
+  p->work_bytes = bytes;
+  return BIP_OK;
+}
+
+GatherArgs gather_args(const bip_plan* p, int side) {
+  GatherArgs g;
+  g.plane_start = p->d_plane_start;
+  g.plane_atoms = p->d_plane_atoms;
+  g.W = p->d_W;
+  g.oy = p->d_oy;
+  g.ox = p->d_ox;
+  g.off = side == 1 ? p->d_off1 : p->d_off2;
+  g.win = side == 1 ? p->d_win1 : p->d_win2;
+  return g;
+}
+
+ReconArgs recon_args(const bip_plan* p, int a, int side) {
+  ReconArgs r;
+  r.win = (side == 1 ? p->d_win1 + p->off1[a] : p->d_win2 + p->off2[a]);
+  r.rowptr = side == 1 ? p->d_rp1 : p->d_rp2;
+  r.col = side == 1 ? p->d_col1 : p->d_col2;
+  r.w = side == 1 ? p->d_w1 : p->d_w2;
+  r.beams = side == 1 ? p->d_beams : p->d_det;
+  r.nb = side == 1 ? p->B : p->ndet;
+  r.W = p->W[a];
+  r.oy = p->oy[a];
+  r.ox = p->ox[a];
+  r.ny = p->g.ny;
+  r.nx = p->g.nx;
+  r.tw = p->d_tw;
+  r.L = p->L;
+  r.retilt_sign = side == 1 ? +1 : -1;
+  r.mode = p->o.recon_mode;
+  return r;
+}
+
+}  // namespace
+}  // namespace bip
+
+using namespace bip;
+
+extern "C" {
+
+const char* bip_last_error(void) { return g_err.c_str(); }
+
+void bip_plan_destroy(bip_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  for (void* a : p->allocations) (void)hipFree(a);
+  if (p->d_work) (void)hipFree(p->d_work);
+  delete p;
+}
+
+int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_atoms,
+                    const double* tau_xyz, const int32_t* win_size, const int32_t* win_origin,
+                    void* stream, bip_plan** out) {
+  if (!out) return err(BIP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!grid || !optics || !tau_xyz || !win_size || !win_origin)
+    return err(BIP_EINVAL, "NULL argument");
+  const bip_grid g = *grid;
+  const bip_optics o = *optics;
+  if (!pow2_in_range(g.ny) || !pow2_in_range(g.nx))
+    return err(BIP_EINVAL, "ny and nx must be powers of two in [64, 1024]");
+  if (g.nz < 1) return err(BIP_EINVAL, "nz must be >= 1");
+  if (!(g.ly > 0) || !(g.lx > 0) || !(g.dz > 0)) return err(BIP_EINVAL, "ly, lx, dz must be > 0");
+  if (!(o.energy_ev > 0) || !(o.alpha_rad > 0) || !(o.theta_rad > 0))
+    return err(BIP_EINVAL, "energy, alpha and theta must be > 0");
+  if (o.partition < 1) return err(BIP_EINVAL, "partition must be >= 1");
+  if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
+    return err(BIP_EINVAL, "unknown recon_mode");
+  if (n_atoms < 1) return err(BIP_EINVAL, "n_atoms must be >= 1");
+  for (int a = 0; a < n_atoms; ++a) {
+    const int W = win_size[a];
+    if (W < 4 || W > std::min(g.ny, g.nx) || W % 4 != 0)
+      return err(BIP_EINVAL, "window size of atom " + std::to_string(a) +
+                                 " must be a multiple of 4 in [4, min(ny, nx)]");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(tau_xyz[3 * a + k]))
+        return err(BIP_EINVAL, "non-finite atom position");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  bip_plan* p = new bip_plan();
+  p->g = g;
+  p->o = o;
+  p->lambda = wavelength(o.energy_ev);
+  p->sigma = interaction(o.energy_ev);
+  p->L = std::max(g.ny, g.nx);
+  p->beams = beams_within(g.ny, g.nx, g.ly, g.lx, o.alpha_rad / p->lambda);
+  p->det = beams_within(g.ny, g.nx, g.ly, g.lx, o.theta_rad / p->lambda);
+  p->B = (int)p->beams.size() / 2;
+  p->ndet = (int)p->det.size() / 2;
+  const double rq = o.theta_rad / p->lambda * g.lx;
+  p->nq_half = (int)std::floor(rq + 1e-12);
+  p->nq = 2 * p->nq_half + 1;
+  int rc = BIP_OK;
+  auto fail = [&](int code) {
+    bip_plan_destroy(p);
+    return code;
+  };
+  if (p->B < 1 || p->ndet < 1) return fail(err(BIP_EINVAL, "empty aperture or detector"));
+  if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
+  if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+  p->Bp1 = (int)p->par1.size() / 2;
+  p->Bp2 = (int)p->par2.size() / 2;
+  // atoms
+  p->n_atoms = n_atoms;
+  p->W.resize(n_atoms);
+  p->oy.resize(n_atoms);
+  p->ox.resize(n_atoms);
+  p->plane.resize(n_atoms);
+  p->off1.resize(n_atoms);
+  p->off2.resize(n_atoms);
+  int64_t o1 = 0, o2 = 0;
+  for (int a = 0; a < n_atoms; ++a) {
+    const int W = win_size[a];
+    p->W[a] = W;
+    p->oy[a] = ((win_origin[2 * a] % g.ny) + g.ny) % g.ny;
+    p->ox[a] = ((win_origin[2 * a + 1] % g.nx) + g.nx) % g.nx;
+    const int pl = (int)std::floor(tau_xyz[3 * a + 2] / g.dz);
+    p->plane[a] = std::min(std::max(pl, 0), g.nz - 1);
+    p->off1[a] = o1;
+    p->off2[a] = o2;
+    o1 += (int64_t)p->Bp1 * W * W;
+    o2 += (int64_t)p->Bp2 * W * W;
+  }
+  p->win1_elems = o1;
+  p->win2_elems = o2;
+  p->plane_start.assign(g.nz + 1, 0);
+  for (int a = 0; a < n_atoms; ++a) p->plane_start[p->plane[a] + 1]++;
+  for (int j = 0; j < g.nz; ++j) p->plane_start[j + 1] += p->plane_start[j];
+  p->plane_atoms.assign(n_atoms, 0);
+  {
+    std::vector<int32_t> fill(p->plane_start.begin(), p->plane_start.end() - 1);
+    for (int a = 0; a < n_atoms; ++a) p->plane_atoms[fill[p->plane[a]]++] = a;
+  }
+  p->i_min = *std::min_element(p->plane.begin(), p->plane.end());
+  p->i_max = *std::max_element(p->plane.begin(), p->plane.end());
+  // device buffers
+  const int64_t G = (int64_t)g.ny * g.nx;
+  std::vector<int2> tmp;
+  auto as_int2 = [](const std::vector<int32_t>& v) {
+    std::vector<int2> r(v.size() / 2);
+    for (size_t i = 0; i < r.size(); ++i) r[i] = make_int2(v[2 * i], v[2 * i + 1]);
+    return r;
+  };
+  std::vector<float> w1f(p->w1.begin(), p->w1.end()), w2f(p->w2.begin(), p->w2.end());
+  if ((rc = dalloc(p, &p->d_tw, p->L)) || (rc = dalloc(p, &p->d_prop, G)) ||
+      (rc = dalloc(p, &p->d_T, G * g.nz)) || (rc = upload(p, &p->d_beams, as_int2(p->beams), st)) ||
+      (rc = upload(p, &p->d_det, as_int2(p->det), st)) ||
+      (rc = upload(p, &p->d_par1, as_int2(p->par1), st)) ||
+      (rc = upload(p, &p->d_par2, as_int2(p->par2), st)) ||
+      (rc = upload(p, &p->d_rp1, p->rp1, st)) || (rc = upload(p, &p->d_col1, p->col1, st)) ||
+      (rc = upload(p, &p->d_w1, w1f, st)) || (rc = upload(p, &p->d_rp2, p->rp2, st)) ||
+      (rc = upload(p, &p->d_col2, p->col2, st)) || (rc = upload(p, &p->d_w2, w2f, st)) ||
+      (rc = upload(p, &p->d_W, p->W, st)) || (rc = upload(p, &p->d_oy, p->oy, st)) ||
+      (rc = upload(p, &p->d_ox, p->ox, st)) || (rc = upload(p, &p->d_off1, p->off1, st)) ||
+      (rc = upload(p, &p->d_off2, p->off2, st)) ||
+      (rc = upload(p, &p->d_plane_start, p->plane_start, st)) ||
+      (rc = upload(p, &p->d_plane_atoms, p->plane_atoms, st)) ||
+      (rc = dalloc(p, &p->d_state1, (size_t)p->Bp1 * G)) ||
+      (rc = dalloc(p, &p->d_state2, (size_t)p->Bp2 * G)) ||
+      (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems)) ||
+      (rc = dalloc(p, &p->d_win2, (size_t)p->win2_elems)))
+    return fail(rc);
+  hipError_t e = launch_twiddles(p->d_tw, p->L, st);
+  if (e == hipSuccess)
+    e = launch_prop_table(p->d_prop, g.ny, g.nx, g.ly, g.lx, p->lambda, g.dz, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(hip_fail(e, "plan tables"));
+  *out = p;
+  return BIP_OK;
+}
+
+int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
+  if (!p || !V) return err(BIP_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const bip_grid& g = p->g;
+  const int64_t G = (int64_t)g.ny * g.nx;
+  HIPCHK(launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st), "transmit");
+  // ---- S1: entrance -> deepest ionization plane
+  HIPCHK(launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st),
+         "init S1");
+  GatherArgs g1 = gather_args(p, 1);
+  for (int j = 0; j <= p->i_max; ++j) {
+    int flags = ROW_GATHER_BEFORE_T;
+    if (j > 0) flags |= ROW_INV;
+    if (j < p->i_max) flags |= ROW_T | ROW_FWD;
+    HIPCHK(launch_row_pass(flags, p->d_state1, p->Bp1, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                           p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], st),
+           "S1 row pass");
+    if (j < p->i_max)
+      HIPCHK(launch_col_pass(p->d_state1, p->Bp1, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st),
+             "S1 column pass");
+  }
+  // ---- S2: exit -> shallowest ionization plane (transpose multislice)
+  HIPCHK(launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
+                                (float)(1.0 / std::sqrt((double)G)), st),
+         "init S2");
+  GatherArgs g2 = gather_args(p, 2);
+  HIPCHK(launch_row_pass(ROW_FWD, p->d_state2, p->Bp2, g.ny, g.nx, nullptr, p->d_tw, p->L,
+                         p->d_par2, -1, g2, 0, 0, st),
+         "S2 row transform");
+  for (int j = g.nz - 1; j >= p->i_min; --j) {
+    HIPCHK(launch_col_pass(p->d_state2, p->Bp2, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st),
+           "S2 column pass");
+    int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
+    if (j > p->i_min) flags |= ROW_FWD;
+    HIPCHK(launch_row_pass(flags, p->d_state2, p->Bp2, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                           p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], st),
+           "S2 row pass");
+  }
+  p->built = true;
+  return BIP_OK;
+}
+
+int bip_parent_windows(bip_plan* p, int32_t atom, int32_t which, float* out, void* stream) {
+  if (!p || !out) return err(BIP_EINVAL, "NULL argument");
+  if (atom < 0 || atom >= p->n_atoms) return err(BIP_EINVAL, "atom out of range");
+  if (which != 1 && which != 2) return err(BIP_EINVAL, "which must be 1 or 2");
+  if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
+  const int W = p->W[atom];
+  const size_t n = (size_t)(which == 1 ? p->Bp1 : p->Bp2) * W * W;
+  const float2* src = which == 1 ? p->d_win1 + p->off1[atom] : p->d_win2 + p->off2[atom];
+  HIPCHK(hipMemcpyAsync(out, src, n * sizeof(float2), hipMemcpyDeviceToDevice, (hipStream_t)stream),
+         "copy windows");
+  return BIP_OK;
+}
+
+int bip_reconstruct_local(bip_plan* p, int32_t atom, float* s1_out, float* s2_out, void* stream) {
+  if (!p) return err(BIP_EINVAL, "NULL plan");
+  if (atom < 0 || atom >= p->n_atoms) return err(BIP_EINVAL, "atom out of range");
+  if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
+  hipStream_t st = (hipStream_t)stream;
+  if (s1_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 1), (float2*)s1_out, st), "recon S1");
+  if (s2_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 2), (float2*)s2_out, st), "recon S2");
+  return BIP_OK;
+}
+
+int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
+                    const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
+                    int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
+                    void* stream) {
+  if (!p || !H || !H_off || !out) return err(BIP_EINVAL, "NULL argument");
+  if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
+  if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
+  if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
+  if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS)
+    return err(BIP_EINVAL, "unknown out_mode");
+  if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16)
+    return err(BIP_EINVAL, "unknown precision");
+  for (int a = 0; a < p->n_atoms; ++a)
+    if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
+      return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
+  std::vector<int32_t> atoms;
+  if (atom_subset) {
+    if (n_subset < 0) return err(BIP_EINVAL, "n_subset < 0");
+    for (int i = 0; i < n_subset; ++i) {
+      if (atom_subset[i] < 0 || atom_subset[i] >= p->n_atoms)
+        return err(BIP_EINVAL, "atom_subset entry out of range");
+      atoms.push_back(atom_subset[i]);
+    }
+  } else {
+    for (int a = 0; a < p->n_atoms; ++a) atoms.push_back(a);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int P = scan_sy * scan_sx;
+  const int64_t Ppad = roundup(P, 128);
+  const int64_t Bpad = roundup(p->B, 32);
+  const int64_t Dpad = roundup(p->ndet, 128);
+  const int64_t csz = precision == BIP_PREC_BF16 ? 4 : 8;  // bytes per complex element
+  const int planes = precision == BIP_PREC_SPLIT_BF16 ? 4 : 2;
+  const int64_t esz = csz * 2 / planes;                     // bytes per plane element
+  // per-atom operand sizes
+  auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };
+  auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };
+  auto atom_bytes = [&](int a) {
+    const int W = p->W[a];
+    return (n1_of(W) * Bpad + Dpad * kd_of(W) + (int64_t)n_ch * Ppad * kd_of(W)) * csz;
+  };
+  const char* env = std::getenv("BIP_WORKSPACE_GB");
+  const double budget_gb = env ? std::atof(env) : 24.0;
+  const int64_t budget = (int64_t)(budget_gb * (1 << 30));
+  const int64_t fixed = Ppad * Bpad * csz + (Dpad / 128) * Ppad * 4 +
+                        (out_mode == BIP_OUT_QEELS ? (int64_t)P * p->ndet * 4 : 0) +
+                        (int64_t)(atoms.size() * n_ch + atoms.size()) * 64 + (1 << 20);
+  // chunking: consecutive atoms while the per-chunk operands fit the budget
+  std::vector<std::pair<int, int>> chunks;
+  int64_t max_chunk = 0;
+  {
+    int b = 0;
+    while (b < (int)atoms.size()) {
+      int e = b;
+      int64_t bytes = 0;
+      while (e < (int)atoms.size() && (e == b || bytes + atom_bytes(atoms[e]) + fixed <= budget)) {
+        bytes += atom_bytes(atoms[e]);
+        ++e;
+      }
+      chunks.push_back({b, e});
+      max_chunk = std::max(max_chunk, bytes);
+      b = e;
+    }
+  }
+  int rc = ensure_work(p, (size_t)(fixed + max_chunk + 16 * 256));
+  if (rc) return rc;
+  Workspace ws{(char*)p->d_work, 0};
+  void* Cm = ws.take(Ppad * Bpad * csz);
+  float* partial = (float*)ws.take((Dpad / 128) * Ppad * 4);
+  float* beams_out = out_mode == BIP_OUT_BEAMS ? out : nullptr;
+  float* beams_tmp = nullptr;
+  if (out_mode == BIP_OUT_QEELS) {
+    beams_tmp = (float*)ws.take((int64_t)P * p->ndet * 4);
+    beams_out = beams_tmp;
+  }
+  GemmJob* d_jobs = (GemmJob*)ws.take(atoms.size() * n_ch * sizeof(GemmJob) + 64);
+  ProbeJob* d_pjobs = (ProbeJob*)ws.take(atoms.size() * sizeof(ProbeJob) + 64);
+  const size_t chunk_base = ws.used;
+  const float cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
+  HIPCHK(launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams, p->B,
+                             scan_sy, scan_sx, cb, st),
+         "illumination");
+  if (out_mode == BIP_OUT_MAP) HIPCHK(launch_zero(out, P, st), "zero");
+  if (beams_out) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
+  // host job tables (uploaded once; chunks index into them)
+  std::vector<GemmJob>& jobs = p->h_jobs;
+  std::vector<ProbeJob>& pjobs = p->h_pjobs;
+  jobs.clear();
+  pjobs.clear();
+  std::vector<int64_t> s1_off, s2_off, u_off;
+  std::vector<int64_t> chunk_s1(chunks.size()), chunk_s2(chunks.size()), chunk_u(chunks.size());
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    int64_t a1 = 0, a2 = 0, au = 0;
+    for (int i = chunks[c].first; i < chunks[c].second; ++i) {
+      const int W = p->W[atoms[i]];
+      s1_off.push_back(a1);
+      s2_off.push_back(a2);
+      u_off.push_back(au);
+      a1 += n1_of(W) * Bpad;
+      a2 += Dpad * kd_of(W);
+      au += (int64_t)n_ch * Ppad * kd_of(W);
+    }
+    chunk_s1[c] = a1;
+    chunk_s2[c] = a2;
+    chunk_u[c] = au;
+  }
+  for (size_t i = 0; i < atoms.size(); ++i) {
+    const int a = atoms[i];
+    const int W = p->W[a];
+    ProbeJob pj;
+    pj.b_off = s1_off[i];
+    pj.u_off = u_off[i];
+    pj.h_off = H_off[a];
+    pj.W2 = W * W;
+    pj.Kd = (int32_t)kd_of(W);
+    pjobs.push_back(pj);
+    for (int n = 0; n < n_ch; ++n) {
+      GemmJob j;
+      j.a_off = s2_off[i];
+      j.b_off = u_off[i] + (int64_t)n * Ppad * kd_of(W);
+      j.K = (int32_t)kd_of(W);
+      j.pad = 0;
+      jobs.push_back(j);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st),
+         "jobs");
+  HIPCHK(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * sizeof(ProbeJob), hipMemcpyHostToDevice,
+                        st),
+         "jobs");
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    ws.used = chunk_base;
+    const int64_t s1_plane = chunk_s1[c], s2_plane = chunk_s2[c], u_plane = chunk_u[c];
+    char* S1op = (char*)ws.take(s1_plane * csz);
+    char* S2op = (char*)ws.take(s2_plane * csz);
+    char* U = (char*)ws.take(u_plane * csz);
+    int max_n1 = 0;
+    for (int i = chunks[c].first; i < chunks[c].second; ++i) {
+      const int a = atoms[i];
+      const int W = p->W[a];
+      max_n1 = std::max<int>(max_n1, (int)n1_of(W));
+      HIPCHK(launch_recon_operand(recon_args(p, a, 1), S1op + s1_off[i] * esz, 0, precision, Bpad,
+                                  n1_of(W), Bpad, s1_plane, st),
+             "recon S1 operand");
+      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2op + s2_off[i] * esz, 1, precision,
+                                  kd_of(W), Dpad, kd_of(W), s2_plane, st),
+             "recon S2 operand");
+    }
+    const int nat = chunks[c].second - chunks[c].first;
+    HIPCHK(launch_probe_gemm(precision, Cm, Ppad * Bpad, (int)Ppad, (int)Bpad, S1op, s1_plane,
+                             max_n1, U, u_plane, (const float2*)H, d_pjobs + chunks[c].first, nat,
+                             n_ch, st),
+           "probe contraction");
+    HIPCHK(launch_det_gemm(precision, out_mode == BIP_OUT_MAP ? BIP_OUT_MAP : BIP_OUT_BEAMS, S2op,
+                           s2_plane, (int)Dpad, U, u_plane, (int)Ppad,
+                           d_jobs + (int64_t)chunks[c].first * n_ch, nat * n_ch, partial,
+                           beams_out, p->ndet, P, st),
+           "detector contraction");
+    if (out_mode == BIP_OUT_MAP)
+      HIPCHK(launch_reduce_map(partial, (int)(Dpad / 128), (int)Ppad, P, out, 1, st), "reduce");
+  }
+  if (out_mode == BIP_OUT_QEELS) {
+    // bins of h_x, each listing its detector beams in detector order
+    std::vector<int32_t>& start = p->h_qstart;
+    std::vector<int32_t>& list = p->h_qlist;
+    start.assign(p->nq + 1, 0);
+    list.clear();
+    std::vector<std::vector<int32_t>> bins(p->nq);
+    for (int d = 0; d < p->ndet; ++d) {
+      const int q = p->det[2 * d + 1] + p->nq_half;
+      if (q >= 0 && q < p->nq) bins[q].push_back(d);
+    }
+    for (int q = 0; q < p->nq; ++q) {
+      start[q + 1] = start[q] + (int)bins[q].size();
+      list.insert(list.end(), bins[q].begin(), bins[q].end());
+    }
+    int32_t* d_start = (int32_t*)ws.take(start.size() * 4);
+    int32_t* d_list = (int32_t*)ws.take(list.size() * 4 + 4);
+    if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "qEELS bin tables exceed the workspace");
+    HIPCHK(hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, st), "bins");
+    HIPCHK(hipMemcpyAsync(d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st), "bins");
+    HIPCHK(launch_qeels_from_beams(beams_tmp, d_start, d_list, p->ndet, P, p->nq, out, st), "qeels");
+  }
+  return BIP_OK;
+}
+
+int bip_query(const bip_plan* p, int32_t what, void* out) {
+  if (!p || !out) return err(BIP_EINVAL, "NULL argument");
+  switch (what) {
+    case BIP_Q_COUNTS: {
+      int64_t* o = (int64_t*)out;
+      o[0] = p->B;
+      o[1] = p->ndet;
+      o[2] = p->Bp1;
+      o[3] = p->Bp2;
+      o[4] = p->nq;
+      o[5] = p->n_atoms;
+      o[6] = (int64_t)p->col1.size();
+      o[7] = (int64_t)p->col2.size();
+      return BIP_OK;
+    }
+    case BIP_Q_BEAMS: std::memcpy(out, p->beams.data(), p->beams.size() * 4); return BIP_OK;
+    case BIP_Q_DETECTOR: std::memcpy(out, p->det.data(), p->det.size() * 4); return BIP_OK;
+    case BIP_Q_PARENTS1: std::memcpy(out, p->par1.data(), p->par1.size() * 4); return BIP_OK;
+    case BIP_Q_PARENTS2: std::memcpy(out, p->par2.data(), p->par2.size() * 4); return BIP_OK;
+    case BIP_Q_PLANES: std::memcpy(out, p->plane.data(), p->plane.size() * 4); return BIP_OK;
+    case BIP_Q_WEIGHTS1:
+    case BIP_Q_WEIGHTS2: {
+      const bool one = what == BIP_Q_WEIGHTS1;
+      const auto& rp = one ? p->rp1 : p->rp2;
+      const auto& cl = one ? p->col1 : p->col2;
+      const auto& w = one ? p->w1 : p->w2;
+      char* o = (char*)out;
+      std::memcpy(o, rp.data(), rp.size() * 4);
+      o += rp.size() * 4;
+      std::memcpy(o, cl.data(), cl.size() * 4);
+      o += cl.size() * 4;
+      std::memcpy(o, w.data(), w.size() * 8);
+      return BIP_OK;
+    }
+    case BIP_Q_SCALARS: {
+      double* o = (double*)out;
+      o[0] = p->lambda;
+      o[1] = p->sigma;
+      o[2] = 0;
+      o[3] = 0;
+      return BIP_OK;
+    }
+    default:
+      return err(BIP_EINVAL, "unknown query");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations of the BiP-PRISM HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bip.h"
+
+namespace bip {
+
+// ------------------------------------------------------------ complex helpers
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------- plan layout
+struct GatherArgs {
+  const int32_t* plane_start;  // [nz + 1] atoms of plane j: plane_atoms[start[j] .. start[j+1])
+  const int32_t* plane_atoms;  // atom ids grouped by plane
+  const int32_t* W;            // [n_atoms]
+  const int32_t* oy;           // [n_atoms]
+  const int32_t* ox;           // [n_atoms]
+  const int64_t* off;          // [n_atoms] element offset of the atom's [Bp][W][W] block
+  float2* win;                 // window stack of this side
+};
+
+struct GemmJob {        // one (atom, channel) pair for the detector contraction
+  int64_t a_off;        // element offset of the A operand (per plane)
+  int64_t b_off;        // element offset of the B operand (per plane)
+  int32_t K;            // padded contraction length
+  int32_t pad;
+};
+struct ProbeJob {       // one atom for the probe synthesis
+  int64_t b_off;        // S1~ operand offset (elements per plane)
+  int64_t u_off;        // output U offset for channel 0 (elements per plane)
+  int64_t h_off;        // H offset (complex elements)
+  int32_t W2;           // W*W
+  int32_t Kd;           // padded detector-contraction length (row pitch of U)
+};
+
+}  // namespace bip
+
+struct bip_plan {
+  bip_grid g;
+  bip_optics o;
+  double lambda = 0, sigma = 0;
+  int L = 0;  // max(ny, nx): size of the twiddle table
+  // geometry (host copies, sorted by (h_y, h_x))
+  std::vector<int32_t> beams, det, par1, par2;  // pairs
+  std::vector<int32_t> rp1, col1, rp2, col2;    // CSR of w(1), w(2)
+  std::vector<double> w1, w2;
+  int B = 0, ndet = 0, Bp1 = 0, Bp2 = 0, nq = 0, nq_half = 0;
+  // atoms
+  int n_atoms = 0;
+  std::vector<int32_t> W, oy, ox, plane;
+  std::vector<int64_t> off1, off2;
+  std::vector<int32_t> plane_start, plane_atoms;
+  int i_min = 0, i_max = 0;
+  bool built = false;
+  // device buffers
+  float2* d_tw = nullptr;       // [L] exp(-2 pi i m / L)
+  float2* d_prop = nullptr;     // [ny][nx] P(q) / G
+  float2* d_T = nullptr;        // [nz][ny][nx]
+  int2* d_beams = nullptr;      // [B]
+  int2* d_det = nullptr;        // [ndet]
+  int2* d_par1 = nullptr;       // [Bp1]
+  int2* d_par2 = nullptr;       // [Bp2]
+  int32_t *d_rp1 = nullptr, *d_col1 = nullptr, *d_rp2 = nullptr, *d_col2 = nullptr;
+  float *d_w1 = nullptr, *d_w2 = nullptr;
+  int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
+  int64_t *d_off1 = nullptr, *d_off2 = nullptr;
+  int32_t *d_plane_start = nullptr, *d_plane_atoms = nullptr;
+  float2* d_state1 = nullptr;   // [Bp1][G]
+  float2* d_state2 = nullptr;   // [Bp2][G]
+  float2* d_win1 = nullptr;     // window stacks
+  float2* d_win2 = nullptr;
+  int64_t win1_elems = 0, win2_elems = 0;
+  // signal workspace (grown on demand)
+  void* d_work = nullptr;
+  size_t work_bytes = 0;
+  // host tables read by asynchronous copies; kept alive until the next call
+  std::vector<bip::GemmJob> h_jobs;
+  std::vector<bip::ProbeJob> h_pjobs;
+  std::vector<int32_t> h_qstart, h_qlist;
+  std::vector<void*> allocations;
+};
+
+namespace bip {
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// ----------------------------------------------------------- launchers
+// setup (k_setup.hip)
+hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
+hipError_t launch_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
+                             double dz, hipStream_t s);
+hipError_t launch_transmit(float2* T, const float* V, int64_t n, float sigma, hipStream_t s);
+hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, int nx,
+                                  const float2* tw, int L, int sign, float scale, hipStream_t s);
+hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p, double* slot_w,
+                         hipStream_t st);
+
+// multislice (k_multislice.hip)
+enum RowFlags { ROW_INV = 1, ROW_T = 2, ROW_FWD = 4, ROW_GATHER_BEFORE_T = 8, ROW_GATHER_AFTER_T = 16 };
+hipError_t launch_row_pass(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
+                           const float2* tw, int L, const int2* parents, int detilt_sign,
+                           const GatherArgs& ga, int gather_begin, int gather_end,
+                           hipStream_t s);
+hipError_t launch_col_pass(float2* state, int ncols, int ny, int nx, const float2* prop,
+                           const float2* tw, int L, hipStream_t s);
+
+// reconstruction (k_recon.hip)
+struct ReconArgs {
+  const float2* win;     // de-tilted parent windows of this atom [Bp][W*W]
+  const int32_t* rowptr; // CSR of the weights
+  const int32_t* col;
+  const float* w;
+  const int2* beams;     // target beams [nb]
+  int nb;                // number of target beams
+  int W, oy, ox;         // window
+  int ny, nx;
+  const float2* tw;
+  int L;
+  int retilt_sign;       // +1: exp(+2 pi i h.r/N) (S1), -1 (S2)
+  int mode;              // BIP_RECON_*
+};
+// plain complex64 output [nb][W*W]
+hipError_t launch_recon_plain(const ReconArgs& a, float2* out, hipStream_t s);
+// GEMM operand outputs; layout kind 0: [r][b] (b fastest, ld = ldk, rows up to nrows)
+// kind 1: [b][r] (r fastest).  prec: BIP_PREC_*; planes at stride plane_stride elements.
+hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int prec, int64_t ld,
+                                int64_t nrows_pad, int64_t ncols_pad, int64_t plane_stride,
+                                hipStream_t s);
+
+// contraction (k_gemm.hip)
+hipError_t launch_probe_gemm(int prec, const void* Cm, int64_t c_plane, int Mpad, int Kb,
+                             const void* S1op, int64_t s1_plane, int Npad,
+                             void* U, int64_t u_plane, const float2* H, const ProbeJob* jobs, int njobs, int n_ch,
+                             hipStream_t s);
+hipError_t launch_det_gemm(int prec, int mode, const void* A, int64_t a_plane, int Mpad,
+                           const void* Bm, int64_t b_plane, int Npad, const GemmJob* jobs,
+                           int njobs, float* partial, float* out_beams, int ndet, int P,
+                           hipStream_t s);
+// illumination matrix Cm [Ppad][Bpad] planes
+hipError_t launch_illumination(void* Cm, int prec, int64_t plane, int Bpad, int Ppad,
+                               const int2* beams, int B, int sy, int sx, float cb, hipStream_t s);
+hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,
+                             int accumulate, hipStream_t s);
+hipError_t launch_qeels_from_beams(const float* beams_out, const int32_t* bin_start,
+                                   const int32_t* bin_list, int ndet, int P, int nq, float* out,
+                                   hipStream_t s);
+hipError_t launch_zero(float* p, int64_t n, hipStream_t s);
+
+}  // namespace bip

@@ -1,0 +1,193 @@
+// Multislice passes over batches of parent columns (step a).
+//
+// A slice step psi <- F^-1[P F[T_j psi]] (eq. propagator, eq.
+// smatrix-advance) is split into two HBM passes over the column stack:
+//   row pass:    [row inverse FFT] -> [window gather] -> x T_j -> [gather]
+//                -> [row FFT]
+//   column pass: column FFT -> x P(q)/G -> column inverse FFT
+// Between passes the state is kept row-transformed (F_row psi), so a row pass
+// fuses the inverse row transform of one step with the forward row transform
+// of the next, and the real-space wave is only ever materialized in
+// registers -- which is where the ionized atoms' windows are cropped.  The S2
+// sweep (transpose multislice, eq. s2) runs the same passes in the other
+// order (column pass, then row pass with T after the propagation).
+#include "fft_core.h"
+
+namespace bip {
+
+namespace {
+
+template <int NX>
+struct RowShape {
+  static constexpr int T = NX / 16;            // threads per row transform
+  static constexpr int ROWS = 256 / T;         // rows per block
+  static constexpr int LDS_ROW = NX + NX / 16; // padded complex elements per row
+};
+
+// Crop the real-space row segment that falls into the windows of the atoms
+// of this plane; de-tilt by exp(-sign 2 pi i h_p.r/N) on the way.
+template <int NX>
+__device__ inline void gather_row(const float2 (&v)[16], int t, int y, int col, int ny,
+                                  const GatherArgs& ga, int gb, int ge, int2 hp,
+                                  const float2* __restrict__ tw, int L, int sign) {
+  constexpr int T = RowShape<NX>::T;
+  for (int q = gb; q < ge; ++q) {
+    const int a = ga.plane_atoms[q];
+    const int W = ga.W[a];
+    int ry = y - ga.oy[a];
+    if (ry < 0) ry += ny;
+    if (ry >= W) continue;
+    float2* dst = ga.win + ga.off[a] + ((int64_t)col * W + ry) * W;
+    const int ox = ga.ox[a];
+    const int my = hp.x * y * (L / ny);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int x = t + T * e;
+      int rx = x - ox;
+      if (rx < 0) rx += NX;
+      if (rx < W) {
+        const int m = (my + hp.y * x * (L / NX)) & (L - 1);
+        const float2 w = tw[m];  // exp(-2 pi i h_p.r/N)
+        dst[rx] = sign > 0 ? cmul(v[e], w) : cmulc(v[e], w);
+      }
+    }
+  }
+}
+
+template <int NX, int FLAGS>
+__global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int ny,
+                                                  const float2* __restrict__ T,
+                                                  const float2* __restrict__ tw, int L,
+                                                  const int2* __restrict__ parents, int sign,
+                                                  GatherArgs ga, int gb, int ge) {
+  using S = RowShape<NX>;
+  __shared__ float2 lds[S::ROWS * S::LDS_ROW];
+  const int t = threadIdx.x % S::T;
+  const int f = threadIdx.x / S::T;
+  const int y = blockIdx.x * S::ROWS + f;
+  const int col = blockIdx.y;
+  float2* row = state + ((int64_t)col * ny + y) * NX;
+  float2* my_lds = lds + f * S::LDS_ROW;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = row[t + S::T * e];
+  if (FLAGS & ROW_INV) fft::transform<NX, true, 1, true>(v, my_lds, t, tw, L);
+  if ((FLAGS & ROW_GATHER_BEFORE_T) && ge > gb)
+    gather_row<NX>(v, t, y, col, ny, ga, gb, ge, parents[col], tw, L, sign);
+  if (FLAGS & ROW_T) {
+    const float2* Trow = T + (int64_t)y * NX;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], Trow[t + S::T * e]);
+  }
+  if ((FLAGS & ROW_GATHER_AFTER_T) && ge > gb)
+    gather_row<NX>(v, t, y, col, ny, ga, gb, ge, parents[col], tw, L, sign);
+  if (FLAGS & ROW_FWD) {
+    fft::transform<NX, false, 1, true>(v, my_lds, t, tw, L);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[t + S::T * e] = v[e];
+  }
+}
+
+template <int NY>
+struct ColShape {
+  static constexpr int T = NY / 16;                       // threads per column transform
+  static constexpr int CB = (NY >= 256) ? 16 : 4096 / NY; // adjacent columns per block
+  static constexpr int THREADS = CB * T;
+};
+
+template <int NY>
+__global__ __launch_bounds__(ColShape<NY>::THREADS) void k_col_pass(
+    float2* __restrict__ state, int nx, const float2* __restrict__ prop,
+    const float2* __restrict__ tw, int L) {
+  using S = ColShape<NY>;
+  __shared__ float2 lds[S::CB * NY];
+  const int c = threadIdx.x % S::CB;
+  const int t = threadIdx.x / S::CB;
+  const int x = blockIdx.x * S::CB + c;
+  const int col = blockIdx.y;
+  float2* base = state + (int64_t)col * NY * nx + x;
+  float2 v[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = base[(int64_t)(t + S::T * e) * nx];
+  fft::transform<NY, false, S::CB, false>(v, lds + c, t, tw, L);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], prop[(int64_t)(t + S::T * e) * nx + x]);
+  fft::transform<NY, true, S::CB, false>(v, lds + c, t, tw, L);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) base[(int64_t)(t + S::T * e) * nx] = v[e];
+}
+
+template <int NX, int FLAGS>
+hipError_t row_launch(float2* state, int ncols, int ny, const float2* T, const float2* tw, int L,
+                      const int2* parents, int sign, const GatherArgs& ga, int gb, int ge,
+                      hipStream_t s) {
+  using S = RowShape<NX>;
+  dim3 grid(ny / S::ROWS, ncols);
+  hipLaunchKernelGGL((k_row_pass<NX, FLAGS>), grid, dim3(256), 0, s, state, ny, T, tw, L, parents,
+                     sign, ga, gb, ge);
+  return hipGetLastError();
+}
+
+template <int NX>
+hipError_t row_dispatch(int flags, float2* state, int ncols, int ny, const float2* T,
+                        const float2* tw, int L, const int2* parents, int sign,
+                        const GatherArgs& ga, int gb, int ge, hipStream_t s) {
+#define ROW_CASE(F) \
+  case F:           \
+    return row_launch<NX, F>(state, ncols, ny, T, tw, L, parents, sign, ga, gb, ge, s);
+  switch (flags) {
+    ROW_CASE(ROW_GATHER_BEFORE_T | ROW_T | ROW_FWD)
+    ROW_CASE(ROW_INV | ROW_GATHER_BEFORE_T | ROW_T | ROW_FWD)
+    ROW_CASE(ROW_INV | ROW_GATHER_BEFORE_T)
+    ROW_CASE(ROW_GATHER_BEFORE_T)
+    ROW_CASE(ROW_FWD)
+    ROW_CASE(ROW_INV | ROW_T | ROW_GATHER_AFTER_T | ROW_FWD)
+    ROW_CASE(ROW_INV | ROW_T | ROW_GATHER_AFTER_T)
+    ROW_CASE(ROW_T | ROW_GATHER_AFTER_T)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef ROW_CASE
+}
+
+}  // namespace
+
+hipError_t launch_row_pass(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
+                           const float2* tw, int L, const int2* parents, int detilt_sign,
+                           const GatherArgs& ga, int gather_begin, int gather_end,
+                           hipStream_t s) {
+  if (ncols == 0) return hipSuccess;
+  switch (nx) {
+    case 64: return row_dispatch<64>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    case 128: return row_dispatch<128>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    case 256: return row_dispatch<256>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    case 512: return row_dispatch<512>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    case 1024: return row_dispatch<1024>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col_pass(float2* state, int ncols, int ny, int nx, const float2* prop,
+                           const float2* tw, int L, hipStream_t s) {
+  if (ncols == 0) return hipSuccess;
+#define COL_CASE(N)                                                                  \
+  case N: {                                                                          \
+    using S = ColShape<N>;                                                           \
+    if (nx % S::CB) return hipErrorInvalidValue;                                     \
+    hipLaunchKernelGGL(k_col_pass<N>, dim3(nx / S::CB, ncols), dim3(S::THREADS), 0, s, \
+                       state, nx, prop, tw, L);                                      \
+    return hipGetLastError();                                                        \
+  }
+  switch (ny) {
+    COL_CASE(64)
+    COL_CASE(128)
+    COL_CASE(256)
+    COL_CASE(512)
+    COL_CASE(1024)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef COL_CASE
+}
+
+}  // namespace bip

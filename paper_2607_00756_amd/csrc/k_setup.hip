@@ -1,0 +1,197 @@
+// Setup kernels: twiddle table, FP64 Fresnel phase table, transmission
+// functions, plane-wave parent columns and the FP64 Sibson geometry.
+#include "bip_internal.h"
+
+namespace bip {
+
+// exp(-2 pi i m / L), evaluated in FP64 and rounded once to complex64.
+__global__ void k_twiddles(float2* tw, int L) {
+  int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= L) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)L, &s, &c);
+  tw[m] = make_float2((float)c, (float)s);
+}
+
+hipError_t launch_twiddles(float2* tw, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3((L + 255) / 256), dim3(256), 0, s, tw, L);
+  return hipGetLastError();
+}
+
+// Fresnel transfer function P(q) = exp(-i pi lambda dz |q|^2) (eq. propagator),
+// divided by G so that the unnormalized inverse FFTs of a step come out
+// normalized.  The phase reaches tens of radians on large grids, so it is
+// formed and reduced in FP64.
+__global__ void k_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
+                             double dz) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y;
+  if (x >= nx) return;
+  int hy = y < ny / 2 ? y : y - ny;
+  int hx = x < nx / 2 ? x : x - nx;
+  double qy = hy / ly, qx = hx / lx;
+  // phase / pi = -lambda dz |q|^2 ; reduce modulo 2 before sincospi
+  double t = -lambda * dz * (qy * qy + qx * qx);
+  t = t - 2.0 * floor(t * 0.5);
+  double s, c;
+  sincospi(t, &s, &c);
+  double g = 1.0 / ((double)ny * (double)nx);
+  prop[(size_t)y * nx + x] = make_float2((float)(c * g), (float)(s * g));
+}
+
+hipError_t launch_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
+                             double dz, hipStream_t s) {
+  hipLaunchKernelGGL(k_prop_table, dim3((nx + 255) / 256, ny), dim3(256), 0, s, prop, ny, nx, ly,
+                     lx, lambda, dz);
+  return hipGetLastError();
+}
+
+// T_j(r) = exp(i sigma V_j(r)) for all slices.
+__global__ void k_transmit(float2* T, const float* __restrict__ V, int64_t n, float sigma) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s, c;
+  sincosf(sigma * V[i], &s, &c);
+  T[i] = make_float2(c, s);
+}
+
+hipError_t launch_transmit(float2* T, const float* V, int64_t n, float sigma, hipStream_t s) {
+  hipLaunchKernelGGL(k_transmit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, V, n,
+                     sigma);
+  return hipGetLastError();
+}
+
+// Plane-wave columns scale * exp(sign 2 pi i h.r/N); the phase index
+// (h_y y L/N_y + h_x x L/N_x) mod L is exact integer arithmetic.
+__global__ void k_init_planewaves(float2* state, const int2* __restrict__ h, int ny, int nx,
+                                  const float2* __restrict__ tw, int L, int sign, float scale) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y;
+  int p = blockIdx.z;
+  if (x >= nx) return;
+  int2 hp = h[p];
+  int m = (hp.x * y * (L / ny) + hp.y * x * (L / nx)) & (L - 1);
+  float2 w = tw[m];                       // exp(-2 pi i m / L)
+  if (sign > 0) w.y = -w.y;
+  state[((size_t)p * ny + y) * nx + x] = cscale(w, scale);
+}
+
+hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, int nx,
+                                  const float2* tw, int L, int sign, float scale, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_planewaves, dim3((nx + 255) / 256, ny, nb), dim3(256), 0, s, state,
+                     h, ny, nx, tw, L, sign, scale);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Sibson
+// Natural-neighbour (Sibson) coordinates of a query beam x against the
+// infinite parent lattice s Z^2 (eq. nnw): w_p = |V+(x) ∩ V(p)| / |V+(x)|,
+// where V+(x) is the Voronoi cell of x after inserting it and V(p) the s x s
+// square cell of lattice point p.  Every lattice point whose square can meet
+// V+(x) lies in the 4 x 4 block around the cell containing x, because V+(x)
+// is within s/sqrt(2) of x.  All geometry is FP64.
+namespace {
+constexpr int kMaxVerts = 24;
+
+struct Poly {
+  double x[kMaxVerts], y[kMaxVerts];
+  int n;
+};
+
+// keep the part of `in` where a*x + b*y <= c
+__device__ inline void clip(const Poly& in, double a, double b, double c, Poly& out) {
+  out.n = 0;
+  for (int i = 0; i < in.n; ++i) {
+    int k = (i + 1 == in.n) ? 0 : i + 1;
+    double px = in.x[i], py = in.y[i], qx = in.x[k], qy = in.y[k];
+    double fp = a * px + b * py - c;
+    double fq = a * qx + b * qy - c;
+    if (fp <= 0.0 && out.n < kMaxVerts) {
+      out.x[out.n] = px;
+      out.y[out.n] = py;
+      ++out.n;
+    }
+    if (((fp < 0.0 && fq > 0.0) || (fp > 0.0 && fq < 0.0)) && out.n < kMaxVerts) {
+      double t = fp / (fp - fq);
+      out.x[out.n] = px + t * (qx - px);
+      out.y[out.n] = py + t * (qy - py);
+      ++out.n;
+    }
+  }
+}
+
+__device__ inline double poly_area(const Poly& p) {
+  if (p.n < 3) return 0.0;
+  double s = 0.0;
+  for (int i = 0; i < p.n; ++i) {
+    int k = (i + 1 == p.n) ? 0 : i + 1;
+    s += p.x[i] * p.y[k] - p.x[k] * p.y[i];
+  }
+  return fabs(s) * 0.5;
+}
+}  // namespace
+
+__global__ void k_sibson(const int2* __restrict__ query, int nq, int s, int2* slot_p,
+                         double* slot_w) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int2 h = query[q];
+  int2* sp = slot_p + (size_t)q * 16;
+  double* sw = slot_w + (size_t)q * 16;
+  // lattice cell of x (floor division valid for negative indices)
+  int cy = (h.x >= 0) ? h.x / s : -((-h.x + s - 1) / s);
+  int cx = (h.y >= 0) ? h.y / s : -((-h.y + s - 1) / s);
+  for (int k = 0; k < 16; ++k) {
+    sp[k] = make_int2((cy + k / 4 - 1) * s, (cx + k % 4 - 1) * s);
+    sw[k] = 0.0;
+  }
+  if (h.x == cy * s && h.y == cx * s) {  // query coincides with a parent
+    sw[5] = 1.0;                           // block offset (1, 1) is (cy, cx)
+    return;
+  }
+  const double x0 = h.x, x1 = h.y, ds = s;
+  Poly a, b;
+  a.n = 4;
+  a.x[0] = x0 - ds; a.y[0] = x1 - ds;
+  a.x[1] = x0 + ds; a.y[1] = x1 - ds;
+  a.x[2] = x0 + ds; a.y[2] = x1 + ds;
+  a.x[3] = x0 - ds; a.y[3] = x1 + ds;
+  for (int k = 0; k < 16; ++k) {
+    double p0 = sp[k].x, p1 = sp[k].y;
+    // |z - x|^2 <= |z - p|^2  <=>  2 (p - x) . z <= |p|^2 - |x|^2
+    clip(a, 2.0 * (p0 - x0), 2.0 * (p1 - x1), p0 * p0 + p1 * p1 - x0 * x0 - x1 * x1, b);
+    a = b;
+  }
+  double total = poly_area(a);
+  for (int k = 0; k < 16; ++k) {
+    double p0 = sp[k].x, p1 = sp[k].y, hs = 0.5 * ds;
+    Poly c, d;
+    clip(a, 1.0, 0.0, p0 + hs, c);
+    clip(c, -1.0, 0.0, -(p0 - hs), d);
+    clip(d, 0.0, 1.0, p1 + hs, c);
+    clip(c, 0.0, -1.0, -(p1 - hs), d);
+    sw[k] = poly_area(d) / total;
+  }
+}
+
+hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p, double* slot_w,
+                         hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sibson, dim3((nq + 127) / 128), dim3(128), 0, st, query, nq, s_lattice,
+                     slot_p, slot_w);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(float* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+hipError_t launch_zero(float* p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace bip
