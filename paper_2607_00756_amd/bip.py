@@ -10,6 +10,9 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its bundled HIP runtime (SONAME libamdhip64.so.7) must be the one
+# libbip.so binds to, so that the process holds a single HIP/HSA runtime.
+import torch  # noqa: F401
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbip.so")
 if not os.path.exists(_LIB_PATH):
@@ -68,7 +71,6 @@ def _check(rc):
 def _stream(stream):
     if stream is not None:
         return ctypes.c_void_p(stream)
-    import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 

@@ -444,7 +444,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   const int64_t Dpad = roundup(p->ndet, 128);
   const int64_t csz = precision == BIP_PREC_BF16 ? 4 : 8;  // bytes per complex element
   const int planes = precision == BIP_PREC_SPLIT_BF16 ? 4 : 2;
-  const int64_t esz = csz * 2 / planes;                     // bytes per plane element
+  const int64_t esz = csz / planes;                         // bytes per plane element
   // per-atom operand sizes
   auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };
   auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };
@@ -547,11 +547,16 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     char* S1op = (char*)ws.take(s1_plane * csz);
     char* S2op = (char*)ws.take(s2_plane * csz);
     char* U = (char*)ws.take(u_plane * csz);
+    if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
     int max_n1 = 0;
     for (int i = chunks[c].first; i < chunks[c].second; ++i) {
       const int a = atoms[i];
       const int W = p->W[a];
       max_n1 = std::max<int>(max_n1, (int)n1_of(W));
+      // every operand block must end inside its plane (offsets are in plane elements)
+      if (s1_off[i] + n1_of(W) * Bpad > s1_plane || s2_off[i] + Dpad * kd_of(W) > s2_plane ||
+          u_off[i] + (int64_t)n_ch * Ppad * kd_of(W) > u_plane)
+        return err(BIP_EINVAL, "internal: operand block outside its buffer");
       HIPCHK(launch_recon_operand(recon_args(p, a, 1), S1op + s1_off[i] * esz, 0, precision, Bpad,
                                   n1_of(W), Bpad, s1_plane, st),
              "recon S1 operand");
