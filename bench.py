@@ -1,0 +1,211 @@
+"""Throughput of the BiP-PRISM EELS map on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--precision split|fp32|bf16] [--config 1]
+
+One step is the whole hot path on the medium synthetic specimen (FCC a = 3.6 A
+in a 40 x 40 x 100 A cell, 256^2 grid, 50 slices of 2 A, 300 keV, 25 mrad
+convergence, 50 mrad collection, partition factor 4, 112 ionized atoms x 9
+transition channels, 64 x 64 scan): parent multislice for S1 and S2 with the
+window gathers (bip_build_smatrix), then windowed reconstruction and the
+contraction into the elemental map (bip_eels_signal).  Inputs are resident in
+HBM before the timed region.  The metric is scan positions x transitions per
+second, one unit being one (scan position, atom, channel) triple.
+
+Prints one JSON line.  It carries the roofline of the dominant kernel (device
+time from HIP events recorded on the launch stream inside the timed region)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "split": 2500.0, "bf16": 2500.0}  # dense MFMA, MI355X
+HBM_PEAK_GBS = 8000.0
+PREC = {"fp32": 0, "split": 1, "bf16": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="split", choices=list(PREC))
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", action="store_true",
+                    help="also time one step of the other precisions and report their error")
+    return ap.parse_args()
+
+
+def cpu_baseline(sp):
+    """Time the FP64 oracle on a bounded sample of the same workload and
+    extrapolate to the whole job (scan positions x transitions per second).
+
+    Sample: (1) parent multislice (S1 to the deepest ionization plane, S2 from
+    the exit to the shallowest) for every 40th parent column of each matrix;
+    (2) windowed reconstruction plus probe-order contraction of one atom, all
+    channels, on 1/16 of the scan positions, fed with random parent windows of
+    the true shapes (timing only).  Full-job time = (1) x 40 + (2) x 16 x atoms."""
+    from oracle import eels as E
+    from oracle import multislice as ms
+    cfg = sp.cfg
+    prob = E.Problem.from_specimen(sp)
+    bip = E.BiP(prob)
+    planes = prob.planes
+    step1 = 40
+    p1 = bip.part1.parents[::step1]
+    p2 = bip.part2.parents[::step1]
+    t0 = time.perf_counter()
+    ms.s1_at_planes(cfg, p1, prob.T, prob.P, [int(planes.max())])
+    ms.s2_at_planes(cfg, p2, prob.T, prob.P, [int(planes.min())])
+    t_sweep = (time.perf_counter() - t0) * step1
+    rng = np.random.default_rng(0)
+    a = 0
+    W = int(sp.win_size[a])
+    y, x = prob.window(a)
+    w1 = rng.normal(size=(bip.part1.n_parents, W, W)) + 1j * rng.normal(size=(bip.part1.n_parents, W, W))
+    w2 = rng.normal(size=(bip.part2.n_parents, W, W)) + 1j * rng.normal(size=(bip.part2.n_parents, W, W))
+    C = E.illumination(cfg, prob.beams)
+    step2 = 16
+    t0 = time.perf_counter()
+    s1 = E.reconstruct(cfg, w1, bip.part1.parents, bip.part1.W, prob.beams, y, x, 1)
+    s2 = E.reconstruct(cfg, w2, bip.part2.parents, bip.part2.W, prob.det, y, x, 2)
+    E.contract_probe_order(s1, s2, prob.H_atom(a), C[::step2])
+    t_atom = (time.perf_counter() - t0) * step2
+    n_atoms = len(sp.tau)
+    t_full = t_sweep + t_atom * n_atoms
+    units = cfg.scan[0] * cfg.scan[1] * n_atoms * sp.n_ch
+    cores = int(os.environ.get("ORACLE_FFT_WORKERS", os.cpu_count() or 1))
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        blas = max([i.get("num_threads", 1) for i in info] + [1])
+        cores = max(cores, blas)
+    except Exception:
+        pass
+    return {
+        "value": units / t_full, "unit": "scan-positions*transitions/s", "cores": cores,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle on config {cfg.name}: parent sweeps of every {step1}th S1/S2 parent "
+                   f"({len(p1)}+{len(p2)} of {bip.part1.n_parents}+{bip.part2.n_parents} columns, all "
+                   f"slices) x{step1}, plus reconstruction+contraction of 1 atom x {sp.n_ch} channels on "
+                   f"1/{step2} of the scans x{step2} x {n_atoms} atoms; extrapolated full-job time "
+                   f"{t_full:.0f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2607_00756_amd import bip, specimen
+
+    dev = torch.device("cuda:0")
+    sp = specimen.make(args.config)
+    cfg = sp.cfg
+    plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin)
+    V = torch.from_numpy(sp.V).to(dev)
+    H = torch.from_numpy(sp.H).to(dev)
+    P = cfg.scan[0] * cfg.scan[1]
+    out = torch.empty(P, dtype=torch.float32, device=dev)
+    prec = PREC[args.precision]
+
+    def step(p=prec, o=out):
+        plan.build_smatrix(V)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, p, o)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    plan.stage_timings(reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    stages = plan.stage_timings(reset=True)
+    plan.set_profiling(False)
+
+    n_atoms = len(sp.tau)
+    units = P * n_atoms * sp.n_ch
+    value = units / (ms_step / 1e3)
+
+    # dominant kernel: detector contraction; algorithmic flops 8 n_det W^2 P per (atom, channel)
+    W2 = sp.win_size.astype(np.int64) ** 2
+    det_flops_step = float(np.sum(8.0 * plan.ndet * W2 * P) * sp.n_ch)
+    det_ms, det_n = stages["det_gemm"]
+    launches_per_step = det_n / args.steps
+    achieved = det_flops_step / launches_per_step / (det_ms / det_n / 1e3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    # multislice: algorithmic 16 G bytes per parent column per slice (one read + one write)
+    G = cfg.ny * cfg.nx
+    planes = plan.query(bip.Q_PLANES)
+    col_slices = plan.Bp1 * int(planes.max()) + plan.Bp2 * (cfg.nz - int(planes.min()))
+    ms_bytes = 16.0 * G * col_slices
+    ms_time = sum(stages[k][0] for k in ("s1_row", "s1_col", "s2_row", "s2_col")) / args.steps
+    res = {
+        "metric": "scan-positions*transitions/s (map, <=1e-4 rel-L2 vs FP64 oracle)",
+        "value": value, "unit": "scan-positions*transitions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "c64 multislice + fp32 MFMA contraction",
+                  "split": "c64 multislice + bf16 hi/lo split MFMA contraction (f32 accumulate)",
+                  "bf16": "c64 multislice + bf16 MFMA contraction (f32 accumulate)"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: FCC 40x40x100 A, {cfg.ny}^2 grid, {cfg.nz} slices, "
+                               f"{cfg.energy_ev/1e3:.0f} keV, {cfg.alpha*1e3:.0f}/{cfg.theta*1e3:.0f} mrad, "
+                               f"s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
+                               f"scan {cfg.scan[0]}x{cfg.scan[1]}, map",
+                   "units_per_step": units, "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1,
+                   "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision},
+        "roofline": {"bound": "mfma", "kernel": "k_det_gemm (detector contraction)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "launches_per_step": launches_per_step,
+                     "avg_launch_ms": det_ms / det_n},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "multislice": {"algorithmic_GB": ms_bytes / 1e9, "ms_per_step": ms_time,
+                       "achieved_GBs": ms_bytes / (ms_time / 1e3) / 1e9,
+                       "frac_of_hbm": ms_bytes / (ms_time / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "wall_s": wall,
+    }
+    if args.compare:
+        ref = out.clone()
+        other = {}
+        for name, pv in PREC.items():
+            if pv == prec:
+                continue
+            o2 = torch.empty_like(out)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            step(pv, o2)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            other[name] = {"ms_per_step": dt * 1e3,
+                           "rel_l2_vs_" + args.precision: float(torch.linalg.norm(o2 - ref) / torch.linalg.norm(ref))}
+        res["other_precisions"] = other
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sp)
+    print(json.dumps(res))
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

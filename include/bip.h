@@ -172,6 +172,24 @@ enum {
 /* bip_query -- copy plan metadata into the host buffer `out`. */
 int bip_query(const bip_plan* plan, int32_t what, void* out);
 
+/*
+ * bip_set_profiling -- when enable != 0, every kernel launch of the plan is
+ * bracketed by HIP events recorded on the caller's stream (adds two event
+ * records per launch; off by default).
+ */
+int bip_set_profiling(bip_plan* plan, int32_t enable);
+
+/*
+ * bip_stage_timings -- device time per stage accumulated while profiling was
+ * on.  Synchronizes the recorded events.  ms, launches: host arrays of
+ * BIP_N_STAGES entries, indexed by BIP_ST_*.  reset != 0 clears the totals.
+ */
+enum {
+  BIP_ST_TRANSMIT = 0, BIP_ST_S1_ROW, BIP_ST_S1_COL, BIP_ST_S2_ROW, BIP_ST_S2_COL, BIP_ST_INIT,
+  BIP_ST_RECON, BIP_ST_ILLUM, BIP_ST_PROBE, BIP_ST_DET, BIP_ST_REDUCE, BIP_N_STAGES
+};
+int bip_stage_timings(bip_plan* plan, double* ms, int64_t* launches, int32_t reset);
+
 /* bip_plan_destroy -- synchronizes and frees every device buffer of the plan. */
 void bip_plan_destroy(bip_plan* plan);
 

@@ -27,7 +27,10 @@ Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_W
     Q_SCALARS = range(9)
 
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
-           "bip_parent_windows", "bip_query", "bip_plan_destroy", "bip_last_error"]
+           "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
+           "bip_plan_destroy", "bip_last_error"]
+STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "illumination",
+          "probe_gemm", "det_gemm", "reduce"]
 
 
 class BipGrid(ctypes.Structure):
@@ -50,10 +53,12 @@ _lib.bip_eels_signal.argtypes = [_p, ctypes.c_int32, _p, _p, _p, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p]
 _lib.bip_parent_windows.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p]
 _lib.bip_query.argtypes = [_p, ctypes.c_int32, _p]
+_lib.bip_set_profiling.argtypes = [_p, ctypes.c_int32]
+_lib.bip_stage_timings.argtypes = [_p, _p, _p, ctypes.c_int32]
 _lib.bip_plan_destroy.argtypes = [_p]
 _lib.bip_plan_destroy.restype = None
 _lib.bip_last_error.restype = ctypes.c_char_p
-for _f in EXPORTS[:6]:
+for _f in EXPORTS[:8]:
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -143,6 +148,17 @@ class Plan:
         _check(_lib.bip_eels_signal(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]),
                                     int(scan[1]), int(out_mode), int(precision), _ptr(out),
                                     _stream(stream)))
+
+    def set_profiling(self, enable):
+        _check(_lib.bip_set_profiling(self._h, 1 if enable else 0))
+
+    def stage_timings(self, reset=True):
+        """{stage: (total ms, launches)} accumulated while profiling was on."""
+        ms = np.zeros(len(STAGES), np.float64)
+        n = np.zeros(len(STAGES), np.int64)
+        _check(_lib.bip_stage_timings(self._h, ms.ctypes.data_as(ctypes.c_void_p),
+                                      n.ctypes.data_as(ctypes.c_void_p), 1 if reset else 0))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
 
     # ------------------------------------------------------------------- query
     def query(self, what):

@@ -53,6 +53,46 @@ int err(int code, const std::string& msg) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+hipEvent_t take_event(bip_plan* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` on stream `st`; when profiling, bracket it with events.
+template <typename F>
+hipError_t timed(bip_plan* p, int stage, hipStream_t st, F&& launch) {
+  if (!p->profiling) return launch();
+  hipEvent_t a = take_event(p), b = take_event(p);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  p->timed.push_back({stage, a, b});
+  return e;
+}
+
+// Fold recorded event pairs into the per-stage totals (synchronizes them).
+int collect_timings(bip_plan* p) {
+  for (auto& t : p->timed) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    p->stage_ms[t.stage] += ms;
+    p->stage_launches[t.stage] += 1;
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->timed.clear();
+  return BIP_OK;
+}
+
 template <typename T>
 int dalloc(bip_plan* p, T** out, size_t count) {
   *out = nullptr;
@@ -221,6 +261,11 @@ void bip_plan_destroy(bip_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   for (void* a : p->allocations) (void)hipFree(a);
+  for (auto& t : p->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   if (p->d_work) (void)hipFree(p->d_work);
   delete p;
 }
@@ -351,37 +396,37 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
-  HIPCHK(launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st), "transmit");
+  HIPCHK(timed(p, ST_TRANSMIT, st, [&] { return launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st); }), "transmit");
   // ---- S1: entrance -> deepest ionization plane
-  HIPCHK(launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st),
+  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st); }),
          "init S1");
   GatherArgs g1 = gather_args(p, 1);
   for (int j = 0; j <= p->i_max; ++j) {
     int flags = ROW_GATHER_BEFORE_T;
     if (j > 0) flags |= ROW_INV;
     if (j < p->i_max) flags |= ROW_T | ROW_FWD;
-    HIPCHK(launch_row_pass(flags, p->d_state1, p->Bp1, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                           p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], st),
+    HIPCHK(timed(p, ST_S1_ROW, st, [&] { return launch_row_pass(flags, p->d_state1, p->Bp1, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                           p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], st); }),
            "S1 row pass");
     if (j < p->i_max)
-      HIPCHK(launch_col_pass(p->d_state1, p->Bp1, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st),
+      HIPCHK(timed(p, ST_S1_COL, st, [&] { return launch_col_pass(p->d_state1, p->Bp1, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
              "S1 column pass");
   }
   // ---- S2: exit -> shallowest ionization plane (transpose multislice)
-  HIPCHK(launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
-                                (float)(1.0 / std::sqrt((double)G)), st),
+  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
+                                (float)(1.0 / std::sqrt((double)G)), st); }),
          "init S2");
   GatherArgs g2 = gather_args(p, 2);
-  HIPCHK(launch_row_pass(ROW_FWD, p->d_state2, p->Bp2, g.ny, g.nx, nullptr, p->d_tw, p->L,
-                         p->d_par2, -1, g2, 0, 0, st),
+  HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, p->d_state2, p->Bp2, g.ny, g.nx, nullptr, p->d_tw, p->L,
+                         p->d_par2, -1, g2, 0, 0, st); }),
          "S2 row transform");
   for (int j = g.nz - 1; j >= p->i_min; --j) {
-    HIPCHK(launch_col_pass(p->d_state2, p->Bp2, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st),
+    HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(p->d_state2, p->Bp2, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
            "S2 column pass");
     int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
     if (j > p->i_min) flags |= ROW_FWD;
-    HIPCHK(launch_row_pass(flags, p->d_state2, p->Bp2, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                           p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], st),
+    HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, p->d_state2, p->Bp2, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                           p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], st); }),
            "S2 row pass");
   }
   p->built = true;
@@ -490,8 +535,8 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   ProbeJob* d_pjobs = (ProbeJob*)ws.take(atoms.size() * sizeof(ProbeJob) + 64);
   const size_t chunk_base = ws.used;
   const float cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
-  HIPCHK(launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams, p->B,
-                             scan_sy, scan_sx, cb, st),
+  HIPCHK(timed(p, ST_ILLUM, st, [&] { return launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams, p->B,
+                             scan_sy, scan_sx, cb, st); }),
          "illumination");
   if (out_mode == BIP_OUT_MAP) HIPCHK(launch_zero(out, P, st), "zero");
   if (beams_out) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
@@ -557,25 +602,25 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       if (s1_off[i] + n1_of(W) * Bpad > s1_plane || s2_off[i] + Dpad * kd_of(W) > s2_plane ||
           u_off[i] + (int64_t)n_ch * Ppad * kd_of(W) > u_plane)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-      HIPCHK(launch_recon_operand(recon_args(p, a, 1), S1op + s1_off[i] * esz, 0, precision, Bpad,
-                                  n1_of(W), Bpad, s1_plane, st),
+      HIPCHK(timed(p, ST_RECON, st, [&] { return launch_recon_operand(recon_args(p, a, 1), S1op + s1_off[i] * esz, 0, precision, Bpad,
+                                  n1_of(W), Bpad, s1_plane, st); }),
              "recon S1 operand");
-      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2op + s2_off[i] * esz, 1, precision,
-                                  kd_of(W), Dpad, kd_of(W), s2_plane, st),
+      HIPCHK(timed(p, ST_RECON, st, [&] { return launch_recon_operand(recon_args(p, a, 2), S2op + s2_off[i] * esz, 1, precision,
+                                  kd_of(W), Dpad, kd_of(W), s2_plane, st); }),
              "recon S2 operand");
     }
     const int nat = chunks[c].second - chunks[c].first;
-    HIPCHK(launch_probe_gemm(precision, Cm, Ppad * Bpad, (int)Ppad, (int)Bpad, S1op, s1_plane,
+    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_gemm(precision, Cm, Ppad * Bpad, (int)Ppad, (int)Bpad, S1op, s1_plane,
                              max_n1, U, u_plane, (const float2*)H, d_pjobs + chunks[c].first, nat,
-                             n_ch, st),
+                             n_ch, st); }),
            "probe contraction");
-    HIPCHK(launch_det_gemm(precision, out_mode == BIP_OUT_MAP ? BIP_OUT_MAP : BIP_OUT_BEAMS, S2op,
+    HIPCHK(timed(p, ST_DET, st, [&] { return launch_det_gemm(precision, out_mode == BIP_OUT_MAP ? BIP_OUT_MAP : BIP_OUT_BEAMS, S2op,
                            s2_plane, (int)Dpad, U, u_plane, (int)Ppad,
                            d_jobs + (int64_t)chunks[c].first * n_ch, nat * n_ch, partial,
-                           beams_out, p->ndet, P, st),
+                           beams_out, p->ndet, P, st); }),
            "detector contraction");
     if (out_mode == BIP_OUT_MAP)
-      HIPCHK(launch_reduce_map(partial, (int)(Dpad / 128), (int)Ppad, P, out, 1, st), "reduce");
+      HIPCHK(timed(p, ST_REDUCE, st, [&] { return launch_reduce_map(partial, (int)(Dpad / 128), (int)Ppad, P, out, 1, st); }), "reduce");
   }
   if (out_mode == BIP_OUT_QEELS) {
     // bins of h_x, each listing its detector beams in detector order
@@ -598,6 +643,27 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     HIPCHK(hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, st), "bins");
     HIPCHK(hipMemcpyAsync(d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st), "bins");
     HIPCHK(launch_qeels_from_beams(beams_tmp, d_start, d_list, p->ndet, P, p->nq, out, st), "qeels");
+  }
+  return BIP_OK;
+}
+
+int bip_set_profiling(bip_plan* p, int32_t enable) {
+  if (!p) return err(BIP_EINVAL, "NULL plan");
+  p->profiling = enable != 0;
+  return BIP_OK;
+}
+
+int bip_stage_timings(bip_plan* p, double* ms, int64_t* launches, int32_t reset) {
+  if (!p || !ms || !launches) return err(BIP_EINVAL, "NULL argument");
+  int rc = collect_timings(p);
+  if (rc) return rc;
+  for (int i = 0; i < ST_COUNT; ++i) {
+    ms[i] = p->stage_ms[i];
+    launches[i] = p->stage_launches[i];
+    if (reset) {
+      p->stage_ms[i] = 0;
+      p->stage_launches[i] = 0;
+    }
   }
   return BIP_OK;
 }

@@ -94,9 +94,21 @@ struct bip_plan {
   std::vector<bip::ProbeJob> h_pjobs;
   std::vector<int32_t> h_qstart, h_qlist;
   std::vector<void*> allocations;
+  // opt-in stage timing with HIP events on the caller's stream
+  bool profiling = false;
+  struct Timed { int stage; hipEvent_t a, b; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[16] = {0};
+  int64_t stage_launches[16] = {0};
 };
 
 namespace bip {
+
+enum Stage {
+  ST_TRANSMIT = 0, ST_S1_ROW, ST_S1_COL, ST_S2_ROW, ST_S2_COL, ST_INIT, ST_RECON, ST_ILLUM,
+  ST_PROBE, ST_DET, ST_REDUCE, ST_COUNT
+};
 
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
