@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--precision", default="split", choices=list(PREC))
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--map-direct", action="store_true",
+                    help="map through the per-beam detector contraction instead of the Gram form")
     ap.add_argument("--compare", action="store_true",
                     help="also time one step of the other precisions and report their error")
     return ap.parse_args()
@@ -124,7 +126,8 @@ def main():
 
     def step(p=prec, o=out):
         plan.build_smatrix(V)
-        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, p, o)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan,
+                         bip.OUT_MAP_DIRECT if args.map_direct else bip.OUT_MAP, p, o)
 
     for _ in range(args.warmup):
         step()
@@ -148,13 +151,25 @@ def main():
     units = P * n_atoms * sp.n_ch
     value = units / (ms_step / 1e3)
 
-    # dominant kernel: detector contraction; algorithmic flops 8 n_det W^2 P per (atom, channel)
-    W2 = sp.win_size.astype(np.int64) ** 2
-    det_flops_step = float(np.sum(8.0 * plan.ndet * W2 * P) * sp.n_ch)
-    det_ms, det_n = stages["det_gemm"]
-    launches_per_step = det_n / args.steps
-    achieved = det_flops_step / launches_per_step / (det_ms / det_n / 1e3) / 1e12
+    # algorithmic flops per step of each contraction stage (unpadded sizes, 8 flops per complex MAC)
+    W2 = sp.win_size.astype(np.float64) ** 2
+    B, nd = plan.B, plan.ndet
+    flops = {"probe_gemm": float(np.sum(8.0 * W2 * B * P))}
+    if args.map_direct:
+        flops["det_gemm"] = float(np.sum(8.0 * nd * W2 * P) * sp.n_ch)
+    else:
+        flops["gram_gemm"] = float(np.sum(8.0 * W2 * W2 * nd))
+        flops["det_gemm"] = float(np.sum(8.0 * W2 * W2 * P))
+    names = {"probe_gemm": "k_zgemm probe synthesis (GEMM-1)",
+             "gram_gemm": "k_zgemm Gram matrix + H correlation",
+             "det_gemm": "k_zgemm detector contraction" if args.map_direct else "k_zgemm quadratic form"}
+    dom = max(flops, key=lambda k: stages[k][0])
+    dom_ms, dom_n = stages[dom]
+    launches_per_step = dom_n / args.steps
+    achieved = flops[dom] / launches_per_step / (dom_ms / dom_n / 1e3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    per_stage_tflops = {k: (flops[k] / (stages[k][0] / args.steps / 1e3) / 1e12 if stages[k][0] > 0 else None)
+                        for k in flops}
     # multislice: algorithmic 16 G bytes per parent column per slice (one read + one write)
     G = cfg.ny * cfg.nx
     planes = plan.query(bip.Q_PLANES)
@@ -175,11 +190,13 @@ def main():
                                f"s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
                                f"scan {cfg.scan[0]}x{cfg.scan[1]}, map",
                    "units_per_step": units, "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1,
-                   "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision},
-        "roofline": {"bound": "mfma", "kernel": "k_det_gemm (detector contraction)",
+                   "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision,
+                   "map_contraction": "direct" if args.map_direct else "gram"},
+        "roofline": {"bound": "mfma", "kernel": names[dom], "stage": dom,
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None, "launches_per_step": launches_per_step,
-                     "avg_launch_ms": det_ms / det_n},
+                     "avg_launch_ms": dom_ms / dom_n},
+        "contraction_tflops": per_stage_tflops,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "multislice": {"algorithmic_GB": ms_bytes / 1e9, "ms_per_step": ms_time,
                        "achieved_GBs": ms_bytes / (ms_time / 1e3) / 1e9,

@@ -50,7 +50,7 @@ enum {
 };
 
 enum { BIP_RECON_MAGNITUDE = 0, BIP_RECON_COMPLEX = 1 };
-enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2 };
+enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2, BIP_OUT_MAP_DIRECT = 3 };
 enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2 };
 
 typedef struct bip_grid {
@@ -186,7 +186,7 @@ int bip_set_profiling(bip_plan* plan, int32_t enable);
  */
 enum {
   BIP_ST_TRANSMIT = 0, BIP_ST_S1_ROW, BIP_ST_S1_COL, BIP_ST_S2_ROW, BIP_ST_S2_COL, BIP_ST_INIT,
-  BIP_ST_RECON, BIP_ST_ILLUM, BIP_ST_PROBE, BIP_ST_DET, BIP_ST_REDUCE, BIP_N_STAGES
+  BIP_ST_RECON, BIP_ST_ILLUM, BIP_ST_PROBE, BIP_ST_DET, BIP_ST_REDUCE, BIP_ST_GRAM, BIP_N_STAGES
 };
 int bip_stage_timings(bip_plan* plan, double* ms, int64_t* launches, int32_t reset);
 

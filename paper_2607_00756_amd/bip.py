@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
-OUT_MAP, OUT_QEELS, OUT_BEAMS = 0, 1, 2
+OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT = 0, 1, 2, 3
 PREC_FP32, PREC_SPLIT_BF16, PREC_BF16 = 0, 1, 2
 Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
     Q_SCALARS = range(9)
@@ -30,7 +30,7 @@ EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
            "bip_plan_destroy", "bip_last_error"]
 STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "illumination",
-          "probe_gemm", "det_gemm", "reduce"]
+          "probe_gemm", "det_gemm", "reduce", "gram_gemm"]
 
 
 class BipGrid(ctypes.Structure):

@@ -464,7 +464,8 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
   if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
-  if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS)
+  if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS &&
+      out_mode != BIP_OUT_MAP_DIRECT)
     return err(BIP_EINVAL, "unknown out_mode");
   if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16)
     return err(BIP_EINVAL, "unknown precision");
@@ -483,26 +484,40 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     for (int a = 0; a < p->n_atoms; ++a) atoms.push_back(a);
   }
   hipStream_t st = (hipStream_t)stream;
+  const bool gram = out_mode == BIP_OUT_MAP;          // map via psi^H Q psi
+  const bool map_direct = out_mode == BIP_OUT_MAP_DIRECT;
   const int P = scan_sy * scan_sx;
   const int64_t Ppad = roundup(P, 128);
   const int64_t Bpad = roundup(p->B, 32);
-  const int64_t Dpad = roundup(p->ndet, 128);
+  const int64_t Dpad = roundup(p->ndet, 128);  // detector rows (direct path)
+  const int64_t Dk = roundup(p->ndet, 32);     // detector as contraction index (Gram path)
   const int64_t csz = precision == BIP_PREC_BF16 ? 4 : 8;  // bytes per complex element
   const int planes = precision == BIP_PREC_SPLIT_BF16 ? 4 : 2;
   const int64_t esz = csz / planes;                         // bytes per plane element
-  // per-atom operand sizes
-  auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };
-  auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };
-  auto atom_bytes = [&](int a) {
-    const int W = p->W[a];
-    return (n1_of(W) * Bpad + Dpad * kd_of(W) + (int64_t)n_ch * Ppad * kd_of(W)) * csz;
+  auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };   // padded window pixels
+  auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };  // ... to whole tiles
+  // per-atom operand blocks (elements per plane), in buffer order
+  auto sizes = [&](int W, int64_t* s) {
+    s[0] = n1_of(W) * Bpad;                                        // S1~ [r][b]
+    s[1] = gram ? n1_of(W) * Dk : Dpad * kd_of(W);                 // S2~^T [r][d] | S2~ [d][r]
+    s[2] = gram ? n1_of(W) * kd_of(W) : (int64_t)n_ch * Ppad * kd_of(W);  // Q [r][r'] | U_n [rho][r]
+    s[3] = gram ? Ppad * kd_of(W) : 0;                             // psi^T [rho][r]
   };
+  auto atom_bytes = [&](int a) {
+    int64_t s[4];
+    sizes(p->W[a], s);
+    return (s[0] + s[1] + s[2] + s[3]) * csz;
+  };
+  int max_n1_all = 0;
+  for (int a : atoms) max_n1_all = std::max<int>(max_n1_all, (int)n1_of(p->W[a]));
+  const int64_t n_partial_tiles = gram ? max_n1_all / 128 : Dpad / 128;
   const char* env = std::getenv("BIP_WORKSPACE_GB");
   const double budget_gb = env ? std::atof(env) : 24.0;
   const int64_t budget = (int64_t)(budget_gb * (1 << 30));
-  const int64_t fixed = Ppad * Bpad * csz + (Dpad / 128) * Ppad * 4 +
+  const int64_t n_jobs_total = (int64_t)atoms.size() * (n_ch + 2);
+  const int64_t fixed = Ppad * Bpad * csz + n_partial_tiles * Ppad * 4 +
                         (out_mode == BIP_OUT_QEELS ? (int64_t)P * p->ndet * 4 : 0) +
-                        (int64_t)(atoms.size() * n_ch + atoms.size()) * 64 + (1 << 20);
+                        n_jobs_total * (int64_t)sizeof(GemmJob) + (1 << 20);
   // chunking: consecutive atoms while the per-chunk operands fit the budget
   std::vector<std::pair<int, int>> chunks;
   int64_t max_chunk = 0;
@@ -524,103 +539,217 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   if (rc) return rc;
   Workspace ws{(char*)p->d_work, 0};
   void* Cm = ws.take(Ppad * Bpad * csz);
-  float* partial = (float*)ws.take((Dpad / 128) * Ppad * 4);
+  float* partial = (float*)ws.take(n_partial_tiles * Ppad * 4);
   float* beams_out = out_mode == BIP_OUT_BEAMS ? out : nullptr;
   float* beams_tmp = nullptr;
   if (out_mode == BIP_OUT_QEELS) {
     beams_tmp = (float*)ws.take((int64_t)P * p->ndet * 4);
     beams_out = beams_tmp;
   }
-  GemmJob* d_jobs = (GemmJob*)ws.take(atoms.size() * n_ch * sizeof(GemmJob) + 64);
-  ProbeJob* d_pjobs = (ProbeJob*)ws.take(atoms.size() * sizeof(ProbeJob) + 64);
+  GemmJob* d_jobs = (GemmJob*)ws.take(n_jobs_total * sizeof(GemmJob) + 64);
   const size_t chunk_base = ws.used;
   const float cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
-  HIPCHK(timed(p, ST_ILLUM, st, [&] { return launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams, p->B,
-                             scan_sy, scan_sx, cb, st); }),
+  HIPCHK(timed(p, ST_ILLUM, st, [&] {
+           return launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams,
+                                      p->B, scan_sy, scan_sx, cb, st);
+         }),
          "illumination");
-  if (out_mode == BIP_OUT_MAP) HIPCHK(launch_zero(out, P, st), "zero");
+  if (out_mode == BIP_OUT_MAP || map_direct) HIPCHK(launch_zero(out, P, st), "zero");
   if (beams_out) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
-  // host job tables (uploaded once; chunks index into them)
-  std::vector<GemmJob>& jobs = p->h_jobs;
-  std::vector<ProbeJob>& pjobs = p->h_pjobs;
-  jobs.clear();
-  pjobs.clear();
-  std::vector<int64_t> s1_off, s2_off, u_off;
-  std::vector<int64_t> chunk_s1(chunks.size()), chunk_s2(chunks.size()), chunk_u(chunks.size());
+  // job tables, chunk-relative offsets; probe jobs, then contraction jobs, then map jobs
+  std::vector<GemmJob>& jprobe = p->h_jobs;
+  std::vector<GemmJob>& jdet = p->h_jobs2;
+  std::vector<GemmJob>& jquad = p->h_jobs3;
+  jprobe.clear();
+  jdet.clear();
+  jquad.clear();
+  std::vector<int64_t> off[4];
+  std::vector<int64_t> chunk_plane[4];
+  for (auto& v : chunk_plane) v.assign(chunks.size(), 0);
   for (size_t c = 0; c < chunks.size(); ++c) {
-    int64_t a1 = 0, a2 = 0, au = 0;
+    int64_t acc[4] = {0, 0, 0, 0};
     for (int i = chunks[c].first; i < chunks[c].second; ++i) {
-      const int W = p->W[atoms[i]];
-      s1_off.push_back(a1);
-      s2_off.push_back(a2);
-      u_off.push_back(au);
-      a1 += n1_of(W) * Bpad;
-      a2 += Dpad * kd_of(W);
-      au += (int64_t)n_ch * Ppad * kd_of(W);
+      int64_t s[4];
+      sizes(p->W[atoms[i]], s);
+      for (int k = 0; k < 4; ++k) {
+        off[k].push_back(acc[k]);
+        acc[k] += s[k];
+      }
     }
-    chunk_s1[c] = a1;
-    chunk_s2[c] = a2;
-    chunk_u[c] = au;
+    for (int k = 0; k < 4; ++k) chunk_plane[k][c] = acc[k];
   }
+  std::vector<int64_t> det_first(atoms.size());
   for (size_t i = 0; i < atoms.size(); ++i) {
     const int a = atoms[i];
     const int W = p->W[a];
-    ProbeJob pj;
-    pj.b_off = s1_off[i];
-    pj.u_off = u_off[i];
-    pj.h_off = H_off[a];
-    pj.W2 = W * W;
-    pj.Kd = (int32_t)kd_of(W);
-    pjobs.push_back(pj);
-    for (int n = 0; n < n_ch; ++n) {
-      GemmJob j;
-      j.a_off = s2_off[i];
-      j.b_off = u_off[i] + (int64_t)n * Ppad * kd_of(W);
-      j.K = (int32_t)kd_of(W);
-      j.pad = 0;
-      jobs.push_back(j);
+    const int32_t W2 = W * W, kd = (int32_t)kd_of(W);
+    GemmJob j{};
+    // probe synthesis: A = illumination [rho][b], B = S1~ [r][b]
+    j.a_off = 0;
+    j.b_off = off[0][i];
+    j.K = (int32_t)Bpad;
+    j.lda = (int32_t)Bpad;
+    j.ldb = (int32_t)Bpad;
+    j.m_lim = (int32_t)Ppad;
+    j.n_lim = W2;
+    j.W2 = W2;
+    j.ldo = kd;
+    j.h_off = H_off[a];
+    j.out_off = gram ? off[3][i] : off[2][i];
+    jprobe.push_back(j);
+    det_first[i] = (int64_t)jdet.size();
+    if (gram) {
+      // Gram: A = B = S2~^T [r][d] (A conjugated), output Q [r][r']
+      GemmJob q{};
+      q.a_off = q.b_off = off[1][i];
+      q.K = q.lda = q.ldb = (int32_t)Dk;
+      q.m_lim = q.n_lim = W2;
+      q.W2 = W2;
+      q.ldo = kd;
+      q.h_off = H_off[a];
+      q.out_off = off[2][i];
+      jdet.push_back(q);
+      // quadratic form: A = psi^T [rho][r'], B = Q [r][r']
+      GemmJob u{};
+      u.a_off = off[3][i];
+      u.b_off = off[2][i];
+      u.K = u.lda = u.ldb = kd;
+      u.m_lim = (int32_t)Ppad;
+      u.n_lim = W2;
+      u.W2 = W2;
+      jquad.push_back(u);
+    } else {
+      for (int n = 0; n < n_ch; ++n) {
+        // detector contraction: A = S2~ [d][r], B = U_n [rho][r]
+        GemmJob d{};
+        d.a_off = off[1][i];
+        d.b_off = off[2][i] + (int64_t)n * Ppad * kd;
+        d.K = d.lda = d.ldb = kd;
+        d.m_lim = (int32_t)Dpad;
+        d.n_lim = (int32_t)Ppad;
+        d.W2 = W2;
+        jdet.push_back(d);
+      }
     }
   }
-  HIPCHK(hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st),
-         "jobs");
-  HIPCHK(hipMemcpyAsync(d_pjobs, pjobs.data(), pjobs.size() * sizeof(ProbeJob), hipMemcpyHostToDevice,
-                        st),
-         "jobs");
+  GemmJob* d_jprobe = d_jobs;
+  GemmJob* d_jdet = d_jprobe + jprobe.size();
+  GemmJob* d_jquad = d_jdet + jdet.size();
+  HIPCHK(hipMemcpyAsync(d_jprobe, jprobe.data(), jprobe.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
+  HIPCHK(hipMemcpyAsync(d_jdet, jdet.data(), jdet.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
+  if (!jquad.empty())
+    HIPCHK(hipMemcpyAsync(d_jquad, jquad.data(), jquad.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   for (size_t c = 0; c < chunks.size(); ++c) {
     ws.used = chunk_base;
-    const int64_t s1_plane = chunk_s1[c], s2_plane = chunk_s2[c], u_plane = chunk_u[c];
-    char* S1op = (char*)ws.take(s1_plane * csz);
-    char* S2op = (char*)ws.take(s2_plane * csz);
-    char* U = (char*)ws.take(u_plane * csz);
+    const int64_t pl0 = chunk_plane[0][c], pl1 = chunk_plane[1][c], pl2 = chunk_plane[2][c],
+                  pl3 = chunk_plane[3][c];
+    char* S1op = (char*)ws.take(pl0 * csz);
+    char* S2op = (char*)ws.take(pl1 * csz);
+    char* X2 = (char*)ws.take(pl2 * csz);   // Q (Gram) or U (direct)
+    char* PsiT = (char*)ws.take(std::max<int64_t>(pl3, 1) * csz);
     if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
     int max_n1 = 0;
-    for (int i = chunks[c].first; i < chunks[c].second; ++i) {
+    const int c0 = chunks[c].first, c1 = chunks[c].second, nat = c1 - c0;
+    for (int i = c0; i < c1; ++i) {
       const int a = atoms[i];
       const int W = p->W[a];
+      int64_t s[4];
+      sizes(W, s);
       max_n1 = std::max<int>(max_n1, (int)n1_of(W));
-      // every operand block must end inside its plane (offsets are in plane elements)
-      if (s1_off[i] + n1_of(W) * Bpad > s1_plane || s2_off[i] + Dpad * kd_of(W) > s2_plane ||
-          u_off[i] + (int64_t)n_ch * Ppad * kd_of(W) > u_plane)
+      if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
+          off[3][i] + s[3] > pl3)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-      HIPCHK(timed(p, ST_RECON, st, [&] { return launch_recon_operand(recon_args(p, a, 1), S1op + s1_off[i] * esz, 0, precision, Bpad,
-                                  n1_of(W), Bpad, s1_plane, st); }),
+      HIPCHK(timed(p, ST_RECON, st, [&] {
+               return launch_recon_operand(recon_args(p, a, 1), S1op + off[0][i] * esz, 0, precision,
+                                           Bpad, n1_of(W), Bpad, pl0, st);
+             }),
              "recon S1 operand");
-      HIPCHK(timed(p, ST_RECON, st, [&] { return launch_recon_operand(recon_args(p, a, 2), S2op + s2_off[i] * esz, 1, precision,
-                                  kd_of(W), Dpad, kd_of(W), s2_plane, st); }),
-             "recon S2 operand");
+      if (gram)
+        HIPCHK(timed(p, ST_RECON, st, [&] {
+                 return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 0, precision,
+                                             Dk, n1_of(W), Dk, pl1, st);
+               }),
+               "recon S2 operand");
+      else
+        HIPCHK(timed(p, ST_RECON, st, [&] {
+                 return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 1, precision,
+                                             kd_of(W), Dpad, kd_of(W), pl1, st);
+               }),
+               "recon S2 operand");
     }
-    const int nat = chunks[c].second - chunks[c].first;
-    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_gemm(precision, Cm, Ppad * Bpad, (int)Ppad, (int)Bpad, S1op, s1_plane,
-                             max_n1, U, u_plane, (const float2*)H, d_pjobs + chunks[c].first, nat,
-                             n_ch, st); }),
+    GemmArgs g{};
+    g.H = (const float2*)H;
+    g.n_ch = n_ch;
+    g.ndet = p->ndet;
+    g.P = P;
+    // probe synthesis for every atom of the chunk (grid z = atom)
+    g.A = Cm;
+    g.a_plane = Ppad * Bpad;
+    g.B = S1op;
+    g.b_plane = pl0;
+    g.jobs = d_jprobe + c0;
+    g.njobs = nat;
+    g.out = gram ? (void*)PsiT : (void*)X2;
+    g.out_plane = gram ? pl3 : pl2;
+    g.Mpad = (int)Ppad;
+    HIPCHK(timed(p, ST_PROBE, st, [&] {
+             return launch_zgemm(precision, gram ? EPI_PSI : EPI_U, g, (int)(Ppad / 128), max_n1 / 128,
+                                 nat, st);
+           }),
            "probe contraction");
-    HIPCHK(timed(p, ST_DET, st, [&] { return launch_det_gemm(precision, out_mode == BIP_OUT_MAP ? BIP_OUT_MAP : BIP_OUT_BEAMS, S2op,
-                           s2_plane, (int)Dpad, U, u_plane, (int)Ppad,
-                           d_jobs + (int64_t)chunks[c].first * n_ch, nat * n_ch, partial,
-                           beams_out, p->ndet, P, st); }),
-           "detector contraction");
-    if (out_mode == BIP_OUT_MAP)
-      HIPCHK(timed(p, ST_REDUCE, st, [&] { return launch_reduce_map(partial, (int)(Dpad / 128), (int)Ppad, P, out, 1, st); }), "reduce");
+    if (gram) {
+      GemmArgs q = g;
+      q.A = S2op;
+      q.a_plane = pl1;
+      q.B = S2op;
+      q.b_plane = pl1;
+      q.jobs = d_jdet + det_first[c0];
+      q.njobs = nat;
+      q.out = X2;
+      q.out_plane = pl2;
+      HIPCHK(timed(p, ST_GRAM, st, [&] {
+               return launch_zgemm(precision, EPI_GRAMQ, q, max_n1 / 128, max_n1 / 128, nat, st);
+             }),
+             "Gram contraction");
+      GemmArgs u = g;
+      u.A = PsiT;
+      u.a_plane = pl3;
+      u.B = X2;
+      u.b_plane = pl2;
+      u.jobs = d_jquad + c0;
+      u.njobs = nat;
+      u.partial = partial;
+      u.Mpad = (int)Ppad;
+      HIPCHK(timed(p, ST_DET, st, [&] {
+               return launch_zgemm(precision, EPI_QUAD, u, (int)(Ppad / 128), max_n1 / 128, 1, st);
+             }),
+             "quadratic form");
+      HIPCHK(timed(p, ST_REDUCE, st, [&] {
+               return launch_reduce_map(partial, max_n1 / 128, (int)Ppad, P, out, 1, st);
+             }),
+             "reduce");
+    } else {
+      GemmArgs d = g;
+      d.A = S2op;
+      d.a_plane = pl1;
+      d.B = X2;
+      d.b_plane = pl2;
+      d.jobs = d_jdet + det_first[c0];
+      d.njobs = nat * n_ch;
+      d.partial = partial;
+      d.out_beams = beams_out;
+      d.Npad = (int)Ppad;
+      HIPCHK(timed(p, ST_DET, st, [&] {
+               return launch_zgemm(precision, map_direct ? EPI_ABS2_MAP : EPI_ABS2_BEAMS, d,
+                                   (int)(Dpad / 128), (int)(Ppad / 128), 1, st);
+             }),
+             "detector contraction");
+      if (map_direct)
+        HIPCHK(timed(p, ST_REDUCE, st, [&] {
+                 return launch_reduce_map(partial, (int)(Dpad / 128), (int)Ppad, P, out, 1, st);
+               }),
+               "reduce");
+    }
   }
   if (out_mode == BIP_OUT_QEELS) {
     // bins of h_x, each listing its detector beams in detector order

@@ -35,20 +35,36 @@ struct GatherArgs {
   float2* win;                 // window stack of this side
 };
 
-struct GemmJob {        // one (atom, channel) pair for the detector contraction
-  int64_t a_off;        // element offset of the A operand (per plane)
-  int64_t b_off;        // element offset of the B operand (per plane)
-  int32_t K;            // padded contraction length
+// One product of the complex contraction kernel (offsets in plane elements).
+struct GemmJob {
+  int64_t a_off, b_off;  // origins of the A and B operands
+  int64_t out_off;       // origin of the output (store epilogues)
+  int64_t h_off;         // first H element of the atom (complex elements)
+  int32_t K;             // contraction length (multiple of the K chunk)
+  int32_t lda, ldb;      // row pitches of A and B
+  int32_t ldo;           // row pitch of the output; columns >= ldo are not written
+  int32_t m_lim, n_lim;  // tiles starting at or beyond these skip the job
+  int32_t W2;            // window pixels of the atom
   int32_t pad;
 };
-struct ProbeJob {       // one atom for the probe synthesis
-  int64_t b_off;        // S1~ operand offset (elements per plane)
-  int64_t u_off;        // output U offset for channel 0 (elements per plane)
-  int64_t h_off;        // H offset (complex elements)
-  int32_t W2;           // W*W
-  int32_t Kd;           // padded detector-contraction length (row pitch of U)
-};
 
+enum Epilogue { EPI_U = 0, EPI_PSI, EPI_ABS2_MAP, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD };
+
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  int64_t a_plane, b_plane;  // plane strides (elements)
+  const GemmJob* jobs;
+  int njobs;
+  void* out;                 // store epilogues
+  int64_t out_plane;
+  const float2* H;           // transition potentials (EPI_U, EPI_GRAMQ)
+  int n_ch;
+  int Mpad, Npad;            // padded extents of the output (map partial pitches)
+  float* partial;            // map partial sums
+  float* out_beams;          // [P][ndet] (EPI_ABS2_BEAMS)
+  int ndet, P;
+};
 }  // namespace bip
 
 struct bip_plan {
@@ -91,7 +107,7 @@ struct bip_plan {
   size_t work_bytes = 0;
   // host tables read by asynchronous copies; kept alive until the next call
   std::vector<bip::GemmJob> h_jobs;
-  std::vector<bip::ProbeJob> h_pjobs;
+  std::vector<bip::GemmJob> h_jobs2, h_jobs3;
   std::vector<int32_t> h_qstart, h_qlist;
   std::vector<void*> allocations;
   // opt-in stage timing with HIP events on the caller's stream
@@ -107,7 +123,7 @@ namespace bip {
 
 enum Stage {
   ST_TRANSMIT = 0, ST_S1_ROW, ST_S1_COL, ST_S2_ROW, ST_S2_COL, ST_INIT, ST_RECON, ST_ILLUM,
-  ST_PROBE, ST_DET, ST_REDUCE, ST_COUNT
+  ST_PROBE, ST_DET, ST_REDUCE, ST_GRAM, ST_COUNT
 };
 
 void set_error(const std::string& msg);
@@ -157,14 +173,9 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
                                 hipStream_t s);
 
 // contraction (k_gemm.hip)
-hipError_t launch_probe_gemm(int prec, const void* Cm, int64_t c_plane, int Mpad, int Kb,
-                             const void* S1op, int64_t s1_plane, int Npad,
-                             void* U, int64_t u_plane, const float2* H, const ProbeJob* jobs, int njobs, int n_ch,
-                             hipStream_t s);
-hipError_t launch_det_gemm(int prec, int mode, const void* A, int64_t a_plane, int Mpad,
-                           const void* Bm, int64_t b_plane, int Npad, const GemmJob* jobs,
-                           int njobs, float* partial, float* out_beams, int ndet, int P,
-                           hipStream_t s);
+hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n_tiles, int z,
+                        hipStream_t s);
+int gemm_bk(int prec);
 // illumination matrix Cm [Ppad][Bpad] planes
 hipError_t launch_illumination(void* Cm, int prec, int64_t plane, int Bpad, int Ppad,
                                const int2* beams, int B, int sy, int sx, float cb, hipStream_t s);

@@ -1,24 +1,37 @@
-// Complex contraction on the matrix cores (step c).
+// Complex contractions on the matrix cores (step c).
 //
-// Both contractions are "NT" complex products C[m][n] = sum_k A[m][k] B[n][k]
-// with K contiguous in both operands, stored as separate real planes:
-//   FP32        : re, im                         (v_mfma_f32_16x16x4_f32)
-//   SPLIT_BF16  : re_hi, re_lo, im_hi, im_lo      (v_mfma_f32_16x16x32_bf16,
+// Every contraction is an "NT" complex product C[m][n] = sum_k A[m][k] B[n][k]
+// (optionally with conj(A)), K contiguous in both operands, each operand
+// stored as separate real planes:
+//   FP32        : re, im                          (v_mfma_f32_16x16x4_f32)
+//   SPLIT_BF16  : re_hi, re_lo, im_hi, im_lo       (v_mfma_f32_16x16x32_bf16;
 //                 hi*hi + hi*lo + lo*hi per real product, FP32 accumulate)
-//   BF16        : re, im                         (v_mfma_f32_16x16x32_bf16)
-// A complex product is four real products (re*re - im*im, re*im + im*re);
-// the minus sign is applied by flipping the sign of the A imaginary
-// fragment.  A workgroup of 4 wave64s owns a 128 x 128 output tile, each
-// wave a 64 x 64 sub-tile of 4 x 4 MFMA blocks; K advances in chunks staged
-// through LDS with the next chunk prefetched into registers.
+//   BF16        : re, im                          (v_mfma_f32_16x16x32_bf16)
+// A complex product is four real products; the minus sign of re*re - im*im is
+// applied by flipping the sign bit of the A imaginary fragment.
 //
-// Probe synthesis (eq. coupling, probe order): psi^T[rho][r] =
-//   sum_b c_b(rho) S1~^b(r); the epilogue multiplies by H_n(r) for every
-//   channel and writes U_n[rho][r] directly in the operand format of the
-//   detector contraction.
-// Detector contraction: A[d][rho] = sum_r S2~^d(r) U_n(r, rho); the epilogue
-//   accumulates |A|^2 over the (atom, channel) jobs of the launch in
-//   registers and then reduces over d (map) or adds into [rho][d] (beams).
+// Tiling: a workgroup of 4 wave64s owns a 128 x 128 output tile (each wave a
+// 64 x 64 sub-tile of 4 x 4 MFMA blocks).  K advances in 64-byte chunks per
+// plane row (16 FP32 or 32 BF16 values).  Operand chunks move from global
+// memory straight into LDS with global_load_lds_dwordx4 (no VGPR staging),
+// double buffered, one barrier per chunk; the 16-byte slots of each LDS row
+// are XOR-swizzled by (row / 4) mod 4 so that the 16 rows read by one MFMA
+// fragment load hit distinct banks.
+//
+// Roles (epilogues):
+//   EPI_U      probe synthesis psi^T[rho][r] = sum_b c_b(rho) S1~^b(r), written
+//              as U_n = H_n psi for every channel (operand of EPI_ABS2_*)
+//   EPI_PSI    probe synthesis written as psi^T itself (operand of EPI_QUAD)
+//   EPI_ABS2_MAP / EPI_ABS2_BEAMS
+//              a_d(rho) = sum_r S2~^d(r) U_n(r, rho); |a|^2 accumulated over
+//              the (atom, channel) jobs in registers, then summed over d (map)
+//              or added into [rho][d] (beams)
+//   EPI_GRAMQ  G[r][r'] = sum_d conj(S2~^d(r)) S2~^d(r') and its product with
+//              sum_n conj(H_n(r)) H_n(r') -> Q (operand of EPI_QUAD)
+//   EPI_QUAD   (Q psi)(r, rho); I(rho) += Re sum_r conj(psi(r, rho)) (Q psi)(r, rho)
+//              accumulated over atoms, then summed over the tile's r
+// For the map, sum_n sum_d |a_d|^2 = psi^H Q psi exactly, which replaces the
+// n_det x N_ch P detector contraction by a W^2 x W^2 Gram matrix per atom.
 #include "bip_internal.h"
 
 namespace bip {
@@ -33,18 +46,30 @@ template <int PREC>
 struct PT;
 template <>
 struct PT<BIP_PREC_FP32> {
-  static constexpr int PLANES = 2, ESZ = 4, BK = 16, PITCH = 20;  // elements
+  static constexpr int PLANES = 2, ESZ = 4, BK = 16;
 };
 template <>
 struct PT<BIP_PREC_SPLIT_BF16> {
-  static constexpr int PLANES = 4, ESZ = 2, BK = 32, PITCH = 40;
+  static constexpr int PLANES = 4, ESZ = 2, BK = 32;
 };
 template <>
 struct PT<BIP_PREC_BF16> {
-  static constexpr int PLANES = 2, ESZ = 2, BK = 32, PITCH = 40;
+  static constexpr int PLANES = 2, ESZ = 2, BK = 32;
 };
 
 constexpr int BM = 128, BN = 128, NTHREADS = 256;
+constexpr int PLANE_TILE = 128 * 64;  // bytes of one plane of one operand tile chunk
+
+template <int PREC>
+constexpr int stage_bytes() {
+  return 2 * PT<PREC>::PLANES * PLANE_TILE;
+}
+template <int PREC>
+constexpr int lds_bytes() {
+  return 2 * stage_bytes<PREC>();
+}
+
+__device__ inline int swz(int row) { return (row >> 2) & 3; }
 
 __device__ inline uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -59,36 +84,33 @@ __device__ inline v8bf neg8(v8bf a) {
   return __builtin_bit_cast(v8bf, u);
 }
 
-// Stage one K chunk of a 128-row operand tile (all planes) into registers.
-// Each plane-row is 64 bytes = 4 x 16-byte segments; 512 segments per plane.
-template <int PREC>
-struct Stage {
-  static constexpr int P = PT<PREC>::PLANES;
-  uint4 r[P][2];
+typedef const __attribute__((address_space(1))) void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
 
-  __device__ inline void load(const char* base, int64_t plane_bytes, int64_t ld_bytes, int k0_bytes,
-                              int tid) {
+// Issue the direct-to-LDS loads of one K chunk of one operand (all planes).
+// Wave w, instruction i covers tile rows 16 (2 w + i) .. +15; lane l writes
+// LDS bytes [16 l, 16 l + 16) of that 1 KB block = row 16 (2w+i) + l/4, slot
+// l%4, which receives global segment (l%4) ^ swz(row).
+template <int PREC>
+__device__ inline void issue_chunk(const char* gbase, int64_t plane_bytes, int64_t ld_bytes,
+                                   int k0_bytes, char* lds_op, int wave, int lane) {
 #pragma unroll
-    for (int p = 0; p < P; ++p)
+  for (int p = 0; p < PT<PREC>::PLANES; ++p)
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int c = tid + NTHREADS * i;
-        const int row = c >> 2, seg = c & 3;
-        r[p][i] = *(const uint4*)(base + p * plane_bytes + row * ld_bytes + k0_bytes + seg * 16);
-      }
-  }
-  __device__ inline void store(char* lds, int tid) const {
-    constexpr int ROWB = PT<PREC>::PITCH * PT<PREC>::ESZ;
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int c = tid + NTHREADS * i;
-        const int row = c >> 2, seg = c & 3;
-        *(uint4*)(lds + (p * 128 + row) * ROWB + seg * 16) = r[p][i];
-      }
-  }
-};
+    for (int i = 0; i < 2; ++i) {
+      const int blk = 2 * wave + i;
+      const int row = 16 * blk + (lane >> 2);
+      const int seg = (lane & 3) ^ swz(row);
+      const char* src = gbase + p * plane_bytes + row * ld_bytes + k0_bytes + seg * 16;
+      char* dst = lds_op + p * PLANE_TILE + blk * 1024;
+      __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)dst, 16, 0, 0);
+    }
+}
+
+template <typename T>
+__device__ inline T lds_frag(const char* lds_op, int plane, int row, int kg) {
+  return *(const T*)(lds_op + plane * PLANE_TILE + row * 64 + ((kg ^ swz(row)) << 4));
+}
 
 struct Acc {
   v4f re[4][4], im[4][4];
@@ -103,24 +125,23 @@ struct Acc {
   }
 };
 
-// Multiply the LDS-resident chunk into the accumulators.
-template <int PREC>
+// Multiply one LDS-resident chunk into the accumulators.
+template <int PREC, bool CONJA>
 __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn, int lane, Acc& acc) {
-  constexpr int ROWB = PT<PREC>::PITCH * PT<PREC>::ESZ;
   const int lr = lane & 15, kg = lane >> 4;
   if constexpr (PREC == BIP_PREC_FP32) {
     float4 bR[4], bI[4];
 #pragma unroll
     for (int bn = 0; bn < 4; ++bn) {
       const int row = wn * 64 + bn * 16 + lr;
-      bR[bn] = *(const float4*)(sB + (0 * 128 + row) * ROWB + kg * 16);
-      bI[bn] = *(const float4*)(sB + (1 * 128 + row) * ROWB + kg * 16);
+      bR[bn] = lds_frag<float4>(sB, 0, row, kg);
+      bI[bn] = lds_frag<float4>(sB, 1, row, kg);
     }
 #pragma unroll
     for (int bm = 0; bm < 4; ++bm) {
       const int row = wm * 64 + bm * 16 + lr;
-      const float4 aR = *(const float4*)(sA + (0 * 128 + row) * ROWB + kg * 16);
-      const float4 aI = *(const float4*)(sA + (1 * 128 + row) * ROWB + kg * 16);
+      const float4 aR = lds_frag<float4>(sA, 0, row, kg);
+      const float4 aI = lds_frag<float4>(sA, 1, row, kg);
       const float ar[4] = {aR.x, aR.y, aR.z, aR.w};
       const float ai[4] = {aI.x, aI.y, aI.z, aI.w};
 #pragma unroll
@@ -129,10 +150,13 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
         const float bi[4] = {bI[bn].x, bI[bn].y, bI[bn].z, bI[bn].w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          // (ar + i s ai)(br + i bi), s = -1 for conj(A)
+          const float ain = CONJA ? ai[q] : -ai[q];
+          const float aip = CONJA ? -ai[q] : ai[q];
           acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[q], br[q], acc.re[bm][bn], 0, 0, 0);
-          acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[q], bi[q], acc.re[bm][bn], 0, 0, 0);
+          acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(ain, bi[q], acc.re[bm][bn], 0, 0, 0);
           acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[q], bi[q], acc.im[bm][bn], 0, 0, 0);
-          acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[q], br[q], acc.im[bm][bn], 0, 0, 0);
+          acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(aip, br[q], acc.im[bm][bn], 0, 0, 0);
         }
       }
     }
@@ -141,36 +165,39 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
 #pragma unroll
     for (int bn = 0; bn < 4; ++bn) {
       const int row = wn * 64 + bn * 16 + lr;
-      bRh[bn] = *(const v8bf*)(sB + (0 * 128 + row) * ROWB + kg * 16);
-      bRl[bn] = *(const v8bf*)(sB + (1 * 128 + row) * ROWB + kg * 16);
-      bIh[bn] = *(const v8bf*)(sB + (2 * 128 + row) * ROWB + kg * 16);
-      bIl[bn] = *(const v8bf*)(sB + (3 * 128 + row) * ROWB + kg * 16);
+      bRh[bn] = lds_frag<v8bf>(sB, 0, row, kg);
+      bRl[bn] = lds_frag<v8bf>(sB, 1, row, kg);
+      bIh[bn] = lds_frag<v8bf>(sB, 2, row, kg);
+      bIl[bn] = lds_frag<v8bf>(sB, 3, row, kg);
     }
 #pragma unroll
     for (int bm = 0; bm < 4; ++bm) {
       const int row = wm * 64 + bm * 16 + lr;
-      const v8bf aRh = *(const v8bf*)(sA + (0 * 128 + row) * ROWB + kg * 16);
-      const v8bf aRl = *(const v8bf*)(sA + (1 * 128 + row) * ROWB + kg * 16);
-      const v8bf aIh = *(const v8bf*)(sA + (2 * 128 + row) * ROWB + kg * 16);
-      const v8bf aIl = *(const v8bf*)(sA + (3 * 128 + row) * ROWB + kg * 16);
+      const v8bf aRh = lds_frag<v8bf>(sA, 0, row, kg);
+      const v8bf aRl = lds_frag<v8bf>(sA, 1, row, kg);
+      const v8bf aIh = lds_frag<v8bf>(sA, 2, row, kg);
+      const v8bf aIl = lds_frag<v8bf>(sA, 3, row, kg);
       const v8bf nIh = neg8(aIh), nIl = neg8(aIl);
+      // the re accumulation takes -aI (+aI for conj(A)); the im one +aI (-aI)
+      const v8bf rIh = CONJA ? aIh : nIh, rIl = CONJA ? aIl : nIl;
+      const v8bf iIh = CONJA ? nIh : aIh, iIl = CONJA ? nIl : aIl;
 #pragma unroll
       for (int bn = 0; bn < 4; ++bn) {
-        v4f r = acc.re[bm][bn], i = acc.im[bm][bn];
+        v4f r = acc.re[bm][bn], m = acc.im[bm][bn];
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRl, bRh[bn], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bRl[bn], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nIl, bIh[bn], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nIh, bIl[bn], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rIl, bIh[bn], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rIh, bIl[bn], r, 0, 0, 0);
         r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bRh[bn], r, 0, 0, 0);
-        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nIh, bIh[bn], r, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRl, bIh[bn], i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bIl[bn], i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIl, bRh[bn], i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIh, bRl[bn], i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bIh[bn], i, 0, 0, 0);
-        i = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aIh, bRh[bn], i, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rIh, bIh[bn], r, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRl, bIh[bn], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bIl[bn], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(iIl, bRh[bn], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(iIh, bRl[bn], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aRh, bIh[bn], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(iIh, bRh[bn], m, 0, 0, 0);
         acc.re[bm][bn] = r;
-        acc.im[bm][bn] = i;
+        acc.im[bm][bn] = m;
       }
     }
   } else {
@@ -178,198 +205,236 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
 #pragma unroll
     for (int bn = 0; bn < 4; ++bn) {
       const int row = wn * 64 + bn * 16 + lr;
-      bR[bn] = *(const v8bf*)(sB + (0 * 128 + row) * ROWB + kg * 16);
-      bI[bn] = *(const v8bf*)(sB + (1 * 128 + row) * ROWB + kg * 16);
+      bR[bn] = lds_frag<v8bf>(sB, 0, row, kg);
+      bI[bn] = lds_frag<v8bf>(sB, 1, row, kg);
     }
 #pragma unroll
     for (int bm = 0; bm < 4; ++bm) {
       const int row = wm * 64 + bm * 16 + lr;
-      const v8bf aR = *(const v8bf*)(sA + (0 * 128 + row) * ROWB + kg * 16);
-      const v8bf aI = *(const v8bf*)(sA + (1 * 128 + row) * ROWB + kg * 16);
+      const v8bf aR = lds_frag<v8bf>(sA, 0, row, kg);
+      const v8bf aI = lds_frag<v8bf>(sA, 1, row, kg);
       const v8bf nI = neg8(aI);
+      const v8bf rI = CONJA ? aI : nI, iI = CONJA ? nI : aI;
 #pragma unroll
       for (int bn = 0; bn < 4; ++bn) {
         acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bR[bn], acc.re[bm][bn], 0, 0, 0);
-        acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nI, bI[bn], acc.re[bm][bn], 0, 0, 0);
+        acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(rI, bI[bn], acc.re[bm][bn], 0, 0, 0);
         acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bI[bn], acc.im[bm][bn], 0, 0, 0);
-        acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bR[bn], acc.im[bm][bn], 0, 0, 0);
+        acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(iI, bR[bn], acc.im[bm][bn], 0, 0, 0);
       }
     }
   }
 }
 
-// Full K loop for one output tile: acc = sum_k A[m0 + .][k] B[n0 + .][k].
-template <int PREC>
+// acc = sum over K of A[m0 + .][k] B[n0 + .][k] (A and B point at the tile origins).
+template <int PREC, bool CONJA>
 __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t lda_b, const char* B,
-                                    int64_t b_plane_b, int64_t ldb_b, int K, char* sA, char* sB,
-                                    int tid, int wm, int wn, int lane, Acc& acc) {
-  constexpr int BKB = PT<PREC>::BK * PT<PREC>::ESZ;  // 64 bytes
+                                    int64_t b_plane_b, int64_t ldb_b, int K, char* lds, int wave,
+                                    int lane, int wm, int wn, Acc& acc) {
+  constexpr int CH = 64;  // bytes per plane row per chunk
+  constexpr int SB = stage_bytes<PREC>();
+  constexpr int OPB = PT<PREC>::PLANES * PLANE_TILE;
   const int nk = K / PT<PREC>::BK;
-  Stage<PREC> sa, sb;
-  sa.load(A, a_plane_b, lda_b, 0, tid);
-  sb.load(B, b_plane_b, ldb_b, 0, tid);
-  sa.store(sA, tid);
-  sb.store(sB, tid);
-  __syncthreads();
+  issue_chunk<PREC>(A, a_plane_b, lda_b, 0, lds, wave, lane);
+  issue_chunk<PREC>(B, b_plane_b, ldb_b, 0, lds + OPB, wave, lane);
   for (int kc = 0; kc < nk; ++kc) {
-    const bool more = kc + 1 < nk;
-    if (more) {
-      sa.load(A, a_plane_b, lda_b, (kc + 1) * BKB, tid);
-      sb.load(B, b_plane_b, ldb_b, (kc + 1) * BKB, tid);
-    }
-    mma_chunk<PREC>(sA, sB, wm, wn, lane, acc);
+    // chunk kc has landed for every wave, and every wave is done with kc - 1
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (more) {
-      sa.store(sA, tid);
-      sb.store(sB, tid);
-      __syncthreads();
+    char* cur = lds + (kc & 1) * SB;
+    if (kc + 1 < nk) {
+      char* nxt = lds + ((kc + 1) & 1) * SB;
+      issue_chunk<PREC>(A, a_plane_b, lda_b, (kc + 1) * CH, nxt, wave, lane);
+      issue_chunk<PREC>(B, b_plane_b, ldb_b, (kc + 1) * CH, nxt + OPB, wave, lane);
     }
+    mma_chunk<PREC, CONJA>(cur, cur + OPB, wm, wn, lane, acc);
   }
+  // all reads of the last buffer finish before the caller reuses LDS
+  __syncthreads();
 }
 
 template <int PREC>
-constexpr int lds_bytes() {
-  return 2 * PT<PREC>::PLANES * 128 * PT<PREC>::PITCH * PT<PREC>::ESZ;
-}
-
-template <int PREC>
-__device__ inline void store_u(void* U, int64_t idx, int64_t plane, float re, float im) {
+__device__ inline void store_planes(void* out, int64_t idx, int64_t plane, float re, float im) {
   if (PREC == BIP_PREC_FP32) {
-    float* o = (float*)U;
+    float* o = (float*)out;
     o[idx] = re;
     o[idx + plane] = im;
   } else if (PREC == BIP_PREC_SPLIT_BF16) {
-    uint16_t* o = (uint16_t*)U;
+    uint16_t* o = (uint16_t*)out;
     const uint16_t rh = f2bf(re), ih = f2bf(im);
     o[idx] = rh;
     o[idx + plane] = f2bf(re - bf2f(rh));
     o[idx + 2 * plane] = ih;
     o[idx + 3 * plane] = f2bf(im - bf2f(ih));
   } else {
-    uint16_t* o = (uint16_t*)U;
+    uint16_t* o = (uint16_t*)out;
     o[idx] = f2bf(re);
     o[idx + plane] = f2bf(im);
   }
 }
 
-// --------------------------------------------------------- probe synthesis
 template <int PREC>
-__global__ __launch_bounds__(NTHREADS) void k_probe_gemm(const void* __restrict__ Cm,
-                                                         int64_t c_plane, int Kb,
-                                                         const void* __restrict__ S1op,
-                                                         int64_t s1_plane, void* __restrict__ U,
-                                                         int64_t u_plane, int64_t Ppad,
-                                                         const float2* __restrict__ H,
-                                                         const ProbeJob* __restrict__ jobs,
-                                                         int n_ch) {
-  extern __shared__ char smem[];
-  constexpr int ESZ = PT<PREC>::ESZ;
-  char* sA = smem;
-  char* sB = smem + lds_bytes<PREC>() / 2;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const ProbeJob job = jobs[blockIdx.z];
-  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
-  if (n0 >= job.W2) return;  // this atom's window has fewer column tiles
-  const char* A = (const char*)Cm + (int64_t)m0 * Kb * ESZ;
-  const char* B = (const char*)S1op + (job.b_off + (int64_t)n0 * Kb) * ESZ;
-  Acc acc;
-  acc.zero();
-  tile_product<PREC>(A, c_plane * ESZ, (int64_t)Kb * ESZ, B, s1_plane * ESZ, (int64_t)Kb * ESZ, Kb,
-                     sA, sB, tid, wm, wn, lane, acc);
-  // epilogue: U_n[rho][r] = H_n(r) psi^T[rho][r]
-  const int lr = lane & 15, kg = lane >> 4;
-#pragma unroll
-  for (int bn = 0; bn < 4; ++bn) {
-    const int r = n0 + wn * 64 + bn * 16 + lr;
-    if (r >= job.Kd) continue;
-#pragma unroll
-    for (int bm = 0; bm < 4; ++bm)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rho = m0 + wm * 64 + bm * 16 + kg * 4 + v;
-        const float pr = acc.re[bm][bn][v], pi = acc.im[bm][bn][v];
-        for (int n = 0; n < n_ch; ++n) {
-          float ur = 0.f, ui = 0.f;
-          if (r < job.W2) {
-            const float2 h = H[job.h_off + (int64_t)n * job.W2 + r];
-            ur = h.x * pr - h.y * pi;
-            ui = h.x * pi + h.y * pr;
-          }
-          store_u<PREC>(U, job.u_off + ((int64_t)n * Ppad + rho) * job.Kd + r, u_plane, ur,
-                        ui);
-        }
-      }
+__device__ inline float2 load_planes(const void* in, int64_t idx, int64_t plane) {
+  if (PREC == BIP_PREC_FP32) {
+    const float* o = (const float*)in;
+    return make_float2(o[idx], o[idx + plane]);
+  } else if (PREC == BIP_PREC_SPLIT_BF16) {
+    const uint16_t* o = (const uint16_t*)in;
+    return make_float2(bf2f(o[idx]) + bf2f(o[idx + plane]),
+                       bf2f(o[idx + 2 * plane]) + bf2f(o[idx + 3 * plane]));
+  } else {
+    const uint16_t* o = (const uint16_t*)in;
+    return make_float2(bf2f(o[idx]), bf2f(o[idx + plane]));
   }
 }
 
-// ------------------------------------------------------ detector contraction
-template <int PREC, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_det_gemm(const void* __restrict__ A, int64_t a_plane,
-                                                       const void* __restrict__ Bm,
-                                                       int64_t b_plane,
-                                                       const GemmJob* __restrict__ jobs, int njobs,
-                                                       float* __restrict__ partial,
-                                                       float* __restrict__ out_beams, int ndet,
-                                                       int P, int Npad) {
+// ------------------------------------------------------------- the kernel
+template <int PREC, int EPI, bool CONJA>
+__global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   extern __shared__ char smem[];
   constexpr int ESZ = PT<PREC>::ESZ;
-  char* sA = smem;
-  char* sB = smem + lds_bytes<PREC>() / 2;
+  constexpr bool ACCUM = (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS || EPI == EPI_QUAD);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
+  const int lr = lane & 15, kg = lane >> 4;
+  // consecutive workgroups (dealt round-robin to the XCDs) take consecutive M
+  // tiles of one N tile
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int jb0 = ACCUM ? 0 : (int)blockIdx.z;
+  const int jb1 = ACCUM ? g.njobs : jb0 + 1;
   v4f sq[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) sq[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int jb = 0; jb < njobs; ++jb) {
-    const GemmJob job = jobs[jb];
-    const char* Ap = (const char*)A + (job.a_off + (int64_t)m0 * job.K) * ESZ;
-    const char* Bp = (const char*)Bm + (job.b_off + (int64_t)n0 * job.K) * ESZ;
-    Acc acc;
-    acc.zero();
-    tile_product<PREC>(Ap, a_plane * ESZ, (int64_t)job.K * ESZ, Bp, b_plane * ESZ,
-                       (int64_t)job.K * ESZ, job.K, sA, sB, tid, wm, wn, lane, acc);
+  if constexpr (ACCUM) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        sq[i][j] += acc.re[i][j] * acc.re[i][j] + acc.im[i][j] * acc.im[i][j];
+      for (int j = 0; j < 4; ++j) sq[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   }
-  const int lr = lane & 15, kg = lane >> 4;
-  if (MODE == BIP_OUT_MAP) {
-    // column sums over the 128 rows (d) of the tile, in a fixed order
-    __shared__ float red[2][BN];
-    float cs[4];
+  for (int jb = jb0; jb < jb1; ++jb) {
+    const GemmJob job = g.jobs[jb];
+    if (n0 >= job.n_lim || m0 >= job.m_lim) continue;  // uniform per workgroup
+    const char* Ap = (const char*)g.A + (job.a_off + (int64_t)m0 * job.lda) * ESZ;
+    const char* Bp = (const char*)g.B + (job.b_off + (int64_t)n0 * job.ldb) * ESZ;
+    Acc acc;
+    acc.zero();
+    tile_product<PREC, CONJA>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
+                              (int64_t)job.ldb * ESZ, job.K, smem, wave, lane, wm, wn, acc);
+    if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
-    for (int bn = 0; bn < 4; ++bn) {
-      float s = 0.f;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm) s += (sq[bm][bn][0] + sq[bm][bn][1]) + (sq[bm][bn][2] + sq[bm][bn][3]);
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      cs[bn] = s;
+        for (int j = 0; j < 4; ++j)
+          sq[i][j] += acc.re[i][j] * acc.re[i][j] + acc.im[i][j] * acc.im[i][j];
+    } else if constexpr (EPI == EPI_QUAD) {
+      // Re conj(psi^T[rho][r]) (Q psi)^T[rho][r]; psi is read back from the A operand
+#pragma unroll
+      for (int bn = 0; bn < 4; ++bn) {
+        const int r = n0 + wn * 64 + bn * 16 + lr;
+        if (r >= job.W2) continue;
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rho = m0 + wm * 64 + bm * 16 + kg * 4 + v;
+            const float2 ps =
+                load_planes<PREC>(g.A, job.a_off + (int64_t)rho * job.lda + r, g.a_plane);
+            sq[bm][bn][v] += ps.x * acc.re[bm][bn][v] + ps.y * acc.im[bm][bn][v];
+          }
+      }
+    } else {
+      // store epilogues: element (m, n) of this tile
+#pragma unroll
+      for (int bn = 0; bn < 4; ++bn) {
+        const int n = n0 + wn * 64 + bn * 16 + lr;
+        if (n >= job.ldo) continue;
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = m0 + wm * 64 + bm * 16 + kg * 4 + v;
+            const float cr = acc.re[bm][bn][v], ci = acc.im[bm][bn][v];
+            if constexpr (EPI == EPI_PSI) {
+              const bool in = n < job.W2;
+              store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane,
+                                 in ? cr : 0.f, in ? ci : 0.f);
+            } else if constexpr (EPI == EPI_U) {
+              for (int c = 0; c < g.n_ch; ++c) {
+                float ur = 0.f, ui = 0.f;
+                if (n < job.W2) {
+                  const float2 h = g.H[job.h_off + (int64_t)c * job.W2 + n];
+                  ur = h.x * cr - h.y * ci;
+                  ui = h.x * ci + h.y * cr;
+                }
+                store_planes<PREC>(g.out, job.out_off + ((int64_t)c * g.Mpad + m) * job.ldo + n,
+                                   g.out_plane, ur, ui);
+              }
+            } else {  // EPI_GRAMQ: m = r, n = r'; Q = G * sum_c conj(H_c(r)) H_c(r')
+              float qr = 0.f, qi = 0.f;
+              if (m < job.W2 && n < job.W2) {
+                float hr = 0.f, hi = 0.f;
+                for (int c = 0; c < g.n_ch; ++c) {
+                  const float2 a = g.H[job.h_off + (int64_t)c * job.W2 + m];
+                  const float2 b = g.H[job.h_off + (int64_t)c * job.W2 + n];
+                  hr += a.x * b.x + a.y * b.y;
+                  hi += a.x * b.y - a.y * b.x;
+                }
+                qr = cr * hr - ci * hi;
+                qi = cr * hi + ci * hr;
+              }
+              store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr,
+                                 qi);
+            }
+          }
+      }
     }
-    __syncthreads();
-    if (kg == 0) {
+  }
+  if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_QUAD) {
+    // map partial sums over the tile's d (rows, ABS2) or r (columns, QUAD), fixed order
+    __shared__ float red[2][128];
+    if constexpr (EPI == EPI_ABS2_MAP) {
+      float cs[4];
 #pragma unroll
-      for (int bn = 0; bn < 4; ++bn) red[wm][wn * 64 + bn * 16 + lr] = cs[bn];
+      for (int bn = 0; bn < 4; ++bn) {
+        float s = 0.f;
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+          s += (sq[bm][bn][0] + sq[bm][bn][1]) + (sq[bm][bn][2] + sq[bm][bn][3]);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        cs[bn] = s;
+      }
+      if (kg == 0) {
+#pragma unroll
+        for (int bn = 0; bn < 4; ++bn) red[wm][wn * 64 + bn * 16 + lr] = cs[bn];
+      }
+      __syncthreads();
+      if (tid < BN) g.partial[(int64_t)blockIdx.x * g.Npad + n0 + tid] = red[0][tid] + red[1][tid];
+    } else {
+      // rows rho = m0 + 64 wm + 16 bm + 4 kg + v; sum over r (lanes lr, blocks bn, waves wn)
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float s = (sq[bm][0][v] + sq[bm][1][v]) + (sq[bm][2][v] + sq[bm][3][v]);
+          s += __shfl_xor(s, 1);
+          s += __shfl_xor(s, 2);
+          s += __shfl_xor(s, 4);
+          s += __shfl_xor(s, 8);
+          if (lr == 0) red[wn][wm * 64 + bm * 16 + kg * 4 + v] = s;
+        }
+      __syncthreads();
+      if (tid < BM) g.partial[(int64_t)blockIdx.y * g.Mpad + m0 + tid] = red[0][tid] + red[1][tid];
     }
-    __syncthreads();
-    if (tid < BN) partial[(int64_t)blockIdx.y * Npad + n0 + tid] = red[0][tid] + red[1][tid];
-  } else {
+  } else if constexpr (EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
     for (int bn = 0; bn < 4; ++bn) {
       const int rho = n0 + wn * 64 + bn * 16 + lr;
-      if (rho >= P) continue;
+      if (rho >= g.P) continue;
 #pragma unroll
       for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int d = m0 + wm * 64 + bm * 16 + kg * 4 + v;
-          if (d < ndet) out_beams[(int64_t)rho * ndet + d] += sq[bm][bn][v];
+          if (d < g.ndet) g.out_beams[(int64_t)rho * g.ndet + d] += sq[bm][bn][v];
         }
     }
   }
@@ -396,7 +461,7 @@ __global__ void k_illumination(void* Cm, int64_t plane, int Bpad, int Ppad,
     re = (float)(cb * c);
     im = (float)(cb * s);
   }
-  store_u<PREC>(Cm, i, plane, re, im);
+  store_planes<PREC>(Cm, i, plane, re, im);
 }
 
 __global__ void k_reduce_map(const float* __restrict__ partial, int ntiles, int Ppad, int P,
@@ -422,70 +487,65 @@ __global__ void k_qeels(const float* __restrict__ beams_out, const int32_t* __re
   out[i] = s;
 }
 
+template <int PREC, int EPI, bool CONJA>
+hipError_t zgemm_launch(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  const void* f = (const void*)k_zgemm<PREC, EPI, CONJA>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_zgemm<PREC, EPI, CONJA>), grid, dim3(NTHREADS), lds_bytes<PREC>(), s, g);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
+  switch (epi) {
+    case EPI_U: return zgemm_launch<PREC, EPI_U, false>(g, grid, s);
+    case EPI_PSI: return zgemm_launch<PREC, EPI_PSI, false>(g, grid, s);
+    case EPI_ABS2_MAP: return zgemm_launch<PREC, EPI_ABS2_MAP, false>(g, grid, s);
+    case EPI_ABS2_BEAMS: return zgemm_launch<PREC, EPI_ABS2_BEAMS, false>(g, grid, s);
+    case EPI_GRAMQ: return zgemm_launch<PREC, EPI_GRAMQ, true>(g, grid, s);
+    case EPI_QUAD: return zgemm_launch<PREC, EPI_QUAD, false>(g, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
-hipError_t launch_probe_gemm(int prec, const void* Cm, int64_t c_plane, int Mpad, int Kb,
-                             const void* S1op, int64_t s1_plane, int Npad, void* U,
-                             int64_t u_plane, const float2* H,
-                             const ProbeJob* jobs, int njobs, int n_ch, hipStream_t s) {
-  if (njobs == 0) return hipSuccess;
-  dim3 grid(Npad / BN, Mpad / BM, njobs);
-#define PG(P)                                                                               \
-  if (prec == P) {                                                                          \
-    hipError_t ea = hipFuncSetAttribute((const void*)k_probe_gemm<P>,                       \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<P>());        \
-    if (ea != hipSuccess) return ea;                                                        \
-    hipLaunchKernelGGL(k_probe_gemm<P>, grid, dim3(NTHREADS), lds_bytes<P>(), s, Cm, c_plane, \
-                       Kb, S1op, s1_plane, U, u_plane, (int64_t)Mpad, H, jobs, n_ch);       \
-    return hipGetLastError();                                                               \
+hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n_tiles, int z,
+                        hipStream_t s) {
+  if (m_tiles <= 0 || n_tiles <= 0 || z <= 0 || g.njobs <= 0) return hipSuccess;
+  const dim3 grid(m_tiles, n_tiles, z);
+  switch (prec) {
+    case BIP_PREC_FP32: return zgemm_prec<BIP_PREC_FP32>(epi, g, grid, s);
+    case BIP_PREC_SPLIT_BF16: return zgemm_prec<BIP_PREC_SPLIT_BF16>(epi, g, grid, s);
+    case BIP_PREC_BF16: return zgemm_prec<BIP_PREC_BF16>(epi, g, grid, s);
+    default: return hipErrorInvalidValue;
   }
-  PG(BIP_PREC_FP32)
-  PG(BIP_PREC_SPLIT_BF16)
-  PG(BIP_PREC_BF16)
-#undef PG
-  return hipErrorInvalidValue;
 }
 
-hipError_t launch_det_gemm(int prec, int mode, const void* A, int64_t a_plane, int Mpad,
-                           const void* Bm, int64_t b_plane, int Npad, const GemmJob* jobs,
-                           int njobs, float* partial, float* out_beams, int ndet, int P,
-                           hipStream_t s) {
-  if (njobs == 0) return hipSuccess;
-  dim3 grid(Npad / BN, Mpad / BM);
-#define DG(PR, MO)                                                                           \
-  if (prec == PR && mode == MO) {                                                            \
-    hipError_t ea = hipFuncSetAttribute((const void*)k_det_gemm<PR, MO>,                     \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PR>());        \
-    if (ea != hipSuccess) return ea;                                                         \
-    hipLaunchKernelGGL((k_det_gemm<PR, MO>), grid, dim3(NTHREADS), lds_bytes<PR>(), s, A,     \
-                       a_plane, Bm, b_plane, jobs, njobs, partial, out_beams, ndet, P, Npad); \
-    return hipGetLastError();                                                                \
-  }
-  DG(BIP_PREC_FP32, BIP_OUT_MAP)
-  DG(BIP_PREC_FP32, BIP_OUT_BEAMS)
-  DG(BIP_PREC_SPLIT_BF16, BIP_OUT_MAP)
-  DG(BIP_PREC_SPLIT_BF16, BIP_OUT_BEAMS)
-  DG(BIP_PREC_BF16, BIP_OUT_MAP)
-  DG(BIP_PREC_BF16, BIP_OUT_BEAMS)
-#undef DG
-  return hipErrorInvalidValue;
-}
+int gemm_bk(int prec) { return prec == BIP_PREC_FP32 ? PT<BIP_PREC_FP32>::BK : 32; }
 
 hipError_t launch_illumination(void* Cm, int prec, int64_t plane, int Bpad, int Ppad,
                                const int2* beams, int B, int sy, int sx, float cb, hipStream_t s) {
   const int64_t n = (int64_t)Ppad * Bpad;
   dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define IL(P)                                                                                    \
-  if (prec == P) {                                                                               \
-    hipLaunchKernelGGL(k_illumination<P>, grid, block, 0, s, Cm, plane, Bpad, Ppad, beams, B, sy, \
-                       sx, cb);                                                                  \
-    return hipGetLastError();                                                                    \
+  switch (prec) {
+    case BIP_PREC_FP32:
+      hipLaunchKernelGGL(k_illumination<BIP_PREC_FP32>, grid, block, 0, s, Cm, plane, Bpad, Ppad,
+                         beams, B, sy, sx, cb);
+      break;
+    case BIP_PREC_SPLIT_BF16:
+      hipLaunchKernelGGL(k_illumination<BIP_PREC_SPLIT_BF16>, grid, block, 0, s, Cm, plane, Bpad,
+                         Ppad, beams, B, sy, sx, cb);
+      break;
+    case BIP_PREC_BF16:
+      hipLaunchKernelGGL(k_illumination<BIP_PREC_BF16>, grid, block, 0, s, Cm, plane, Bpad, Ppad,
+                         beams, B, sy, sx, cb);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  IL(BIP_PREC_FP32)
-  IL(BIP_PREC_SPLIT_BF16)
-  IL(BIP_PREC_BF16)
-#undef IL
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,

@@ -21,7 +21,7 @@ from tests.gpu_helpers import gpu_run, make_plan, rel_l2, torch_dev
 pytestmark = pytest.mark.gpu
 
 FP32, SPLIT, BF16 = 0, 1, 2
-MAP, QEELS, BEAMS = 0, 1, 2
+MAP, QEELS, BEAMS, MAP_DIRECT = 0, 1, 2, 3
 
 
 def _bip():
@@ -109,12 +109,12 @@ def test_c0_reconstruct_local(c0, mode):
 
 
 @pytest.mark.parametrize("prec", [FP32, SPLIT, BF16])
-@pytest.mark.parametrize("out_mode", [MAP, QEELS, BEAMS])
+@pytest.mark.parametrize("out_mode", [MAP, QEELS, BEAMS, MAP_DIRECT])
 def test_c0_signal(c0, prec, out_mode):
     sp = c0["sp"]
     got, plan = gpu_run(sp.cfg, sp.V, sp.tau, sp.win_size, sp.win_origin, sp.H, sp.H_off, sp.n_ch,
                         out_mode, prec)
-    want = c0[("out", out_mode)]
+    want = c0[("out", MAP if out_mode == MAP_DIRECT else out_mode)]
     err = rel_l2(got, want)
     print(f"[c0 signal prec {prec} mode {out_mode}] rel-L2 vs FP64 oracle {err:.3e}")
     assert got.shape == want.shape
@@ -127,6 +127,20 @@ def _ragged_problem(s=2, recon=E.RECON_MAGNITUDE):
     tp = tiny_problem(cfg, n_atoms=5, n_ch=2, W=8, seed=11, vscale=25.0, planes=[0, 4, 2, 2, 1],
                       win_sizes=[4, 12, 16, 24, 64])
     return cfg, tp
+
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+@pytest.mark.parametrize("prec", [FP32, SPLIT])
+def test_ragged_windows_and_tiles_map(s, prec):
+    """Map through the Gram reordering on ragged windows (W = 4 .. 64)."""
+    cfg, tp = _ragged_problem(s)
+    prob = as_oracle_problem(tp)
+    want = E.BiP(prob).run(mode=E.OUT_MAP)
+    got, plan = gpu_run(cfg, tp.V, tp.tau, tp.win_size, tp.win_origin, tp.H, tp.H_off, tp.n_ch,
+                        MAP, prec)
+    err = rel_l2(got, want)
+    print(f"[ragged map s={s} prec {prec}] rel-L2 {err:.3e}")
+    assert err < 1e-4
 
 
 @pytest.mark.parametrize("s", [1, 2, 3])
