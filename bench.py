@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "split": 2500.0, "bf16": 2500.0}  # dense MFMA, MI355X
+ALU_PEAK_TFLOPS = 157.3   # FP32 vector FMA, 256 CUs at 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 PREC = {"fp32": 0, "split": 1, "bf16": 2}
 
@@ -151,27 +152,45 @@ def main():
     units = P * n_atoms * sp.n_ch
     value = units / (ms_step / 1e3)
 
-    # algorithmic flops per step of each contraction stage (unpadded sizes, 8 flops per complex MAC)
+    # algorithmic work per step of each timed stage: (amount, unit, bound, peak)
     W2 = sp.win_size.astype(np.float64) ** 2
     B, nd = plan.B, plan.ndet
-    flops = {"probe_gemm": float(np.sum(8.0 * W2 * B * P))}
+    Sy, Sx = cfg.scan
+    G = cfg.ny * cfg.nx
+    csz = 4 if args.precision == "bf16" else 8
+    mfma_peak = PEAK_TFLOPS[args.precision]
+    work = {
+        # fold (fused S1~ reconstruction, not counted) + DFT over x, then DFT over y
+        "probe_fold": (float(np.sum(8.0 * W2 * P * Sx)) / 1e12, "TFLOP/s", "alu", ALU_PEAK_TFLOPS),
+        "probe_dft": (float(np.sum(8.0 * W2 * P * Sy)) / 1e12, "TFLOP/s", "alu", ALU_PEAK_TFLOPS),
+        # S2~ written once in the operand planes, parent windows read once
+        "recon": (float(np.sum(W2 * (nd * csz + plan.Bp2 * 8))) / 1e9, "GB/s", "hbm", HBM_PEAK_GBS),
+    }
     if args.map_direct:
-        flops["det_gemm"] = float(np.sum(8.0 * nd * W2 * P) * sp.n_ch)
+        work["det_gemm"] = (float(np.sum(8.0 * nd * W2 * P) * sp.n_ch) / 1e12, "TFLOP/s", "mfma", mfma_peak)
     else:
-        flops["gram_gemm"] = float(np.sum(8.0 * W2 * W2 * nd))
-        flops["det_gemm"] = float(np.sum(8.0 * W2 * W2 * P))
-    names = {"probe_gemm": "k_zgemm probe synthesis (GEMM-1)",
+        work["gram_gemm"] = (float(np.sum(8.0 * W2 * W2 * nd)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
+        work["det_gemm"] = (float(np.sum(8.0 * W2 * W2 * P)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
+    # parent sweeps: every pass reads and writes the whole state of its columns
+    for st, ncol in (("s1_row", plan.Bp1), ("s1_col", plan.Bp1), ("s2_row", plan.Bp2), ("s2_col", plan.Bp2)):
+        work[st] = (16.0 * G * ncol * stages[st][1] / args.steps / 1e9, "GB/s", "hbm", HBM_PEAK_GBS)
+    names = {"probe_fold": "k_probe_fold_x (S1~ reconstruction + residue fold + DFT over x)",
+             "probe_dft": "k_probe_y (DFT over y, operand store)",
+             "recon": "k_recon_operand (S2~ reconstruction)",
              "gram_gemm": "k_zgemm Gram matrix + H correlation",
-             "det_gemm": "k_zgemm detector contraction" if args.map_direct else "k_zgemm quadratic form"}
-    dom = max(flops, key=lambda k: stages[k][0])
+             "det_gemm": "k_zgemm detector contraction" if args.map_direct else "k_zgemm quadratic form",
+             "s1_row": "k_row_pass (S1)", "s1_col": "k_col_pass (S1)",
+             "s2_row": "k_row_pass (S2)", "s2_col": "k_col_pass (S2)"}
+    dom = max(work, key=lambda k: stages[k][0])
     dom_ms, dom_n = stages[dom]
     launches_per_step = dom_n / args.steps
-    achieved = flops[dom] / launches_per_step / (dom_ms / dom_n / 1e3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    per_stage_tflops = {k: (flops[k] / (stages[k][0] / args.steps / 1e3) / 1e12 if stages[k][0] > 0 else None)
-                        for k in flops}
-    # multislice: algorithmic 16 G bytes per parent column per slice (one read + one write)
-    G = cfg.ny * cfg.nx
+    amount, unit, bound, peak = work[dom]
+    achieved = amount / launches_per_step / (dom_ms / dom_n / 1e3)
+    per_stage = {k: {"rate": (w[0] / (stages[k][0] / args.steps / 1e3) if stages[k][0] > 0 else None),
+                     "unit": w[1], "bound": w[2], "frac": (w[0] / (stages[k][0] / args.steps / 1e3) / w[3]
+                                                            if stages[k][0] > 0 else None)}
+                 for k, w in work.items()}
+    # multislice as a whole: algorithmic 16 G bytes per parent column per slice
     planes = plan.query(bip.Q_PLANES)
     col_slices = plan.Bp1 * int(planes.max()) + plan.Bp2 * (cfg.nz - int(planes.min()))
     ms_bytes = 16.0 * G * col_slices
@@ -192,11 +211,11 @@ def main():
                    "units_per_step": units, "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1,
                    "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision,
                    "map_contraction": "direct" if args.map_direct else "gram"},
-        "roofline": {"bound": "mfma", "kernel": names[dom], "stage": dom,
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+        "roofline": {"bound": bound, "kernel": names[dom], "stage": dom,
+                     "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                      "traffic": None, "launches_per_step": launches_per_step,
                      "avg_launch_ms": dom_ms / dom_n},
-        "contraction_tflops": per_stage_tflops,
+        "stage_rooflines": per_stage,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "multislice": {"algorithmic_GB": ms_bytes / 1e9, "ms_per_step": ms_time,
                        "achieved_GBs": ms_bytes / (ms_time / 1e3) / 1e9,

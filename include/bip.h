@@ -141,7 +141,10 @@ int bip_reconstruct_local(bip_plan* plan, int32_t atom, float* s1_out, float* s2
  *                bf16 products, FP32 accumulate) or BIP_PREC_BF16.
  *   out          device f32, overwritten.
  * Probe coefficients are c_b = 1/sqrt(G B) (unit-norm probe, no aberrations).
- * Errors: BIP_EINVAL, BIP_ESTATE (no build), BIP_ENOMEM, BIP_EHIP.
+ * The probe sum over beams is evaluated exactly as a fold of the beams by
+ * (h_y mod S_y, h_x mod S_x) followed by an S_y x S_x DFT over the raster.
+ * Errors: BIP_EINVAL, BIP_ESTATE (no build), BIP_ENOMEM, BIP_EHIP,
+ * BIP_EUNSUPPORTED (S_y or S_x above 256).
  */
 int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t* H_off,
                     const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
@@ -183,10 +186,17 @@ int bip_set_profiling(bip_plan* plan, int32_t enable);
  * bip_stage_timings -- device time per stage accumulated while profiling was
  * on.  Synchronizes the recorded events.  ms, launches: host arrays of
  * BIP_N_STAGES entries, indexed by BIP_ST_*.  reset != 0 clears the totals.
+ * Stages: TRANSMIT exp(i sigma V); S1_ROW / S1_COL and S2_ROW / S2_COL the
+ * row and column FFT passes of the two parent sweeps (window gathers fused
+ * into the row passes); INIT plane-wave parents; RECON S2~ reconstruction;
+ * FOLD S1~ reconstruction fused with the residue fold and the first DFT of
+ * the probe synthesis; PROBE its second DFT and operand store; DET the
+ * detector contraction (beams, qEELS, direct map) or the quadratic form of
+ * the map; REDUCE map partial sums; GRAM the Gram matrix of S2~.
  */
 enum {
   BIP_ST_TRANSMIT = 0, BIP_ST_S1_ROW, BIP_ST_S1_COL, BIP_ST_S2_ROW, BIP_ST_S2_COL, BIP_ST_INIT,
-  BIP_ST_RECON, BIP_ST_ILLUM, BIP_ST_PROBE, BIP_ST_DET, BIP_ST_REDUCE, BIP_ST_GRAM, BIP_N_STAGES
+  BIP_ST_RECON, BIP_ST_FOLD, BIP_ST_PROBE, BIP_ST_DET, BIP_ST_REDUCE, BIP_ST_GRAM, BIP_N_STAGES
 };
 int bip_stage_timings(bip_plan* plan, double* ms, int64_t* launches, int32_t reset);
 

@@ -29,8 +29,8 @@ Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_W
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
            "bip_plan_destroy", "bip_last_error"]
-STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "illumination",
-          "probe_gemm", "det_gemm", "reduce", "gram_gemm"]
+STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "probe_fold",
+          "probe_dft", "det_gemm", "reduce", "gram_gemm"]
 
 
 class BipGrid(ctypes.Structure):

@@ -464,6 +464,8 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
   if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
+  if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)
+    return err(BIP_EUNSUPPORTED, "scan raster sides above " + std::to_string(BIP_MAX_SCAN));
   if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS &&
       out_mode != BIP_OUT_MAP_DIRECT)
     return err(BIP_EINVAL, "unknown out_mode");
@@ -488,7 +490,6 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   const bool map_direct = out_mode == BIP_OUT_MAP_DIRECT;
   const int P = scan_sy * scan_sx;
   const int64_t Ppad = roundup(P, 128);
-  const int64_t Bpad = roundup(p->B, 32);
   const int64_t Dpad = roundup(p->ndet, 128);  // detector rows (direct path)
   const int64_t Dk = roundup(p->ndet, 32);     // detector as contraction index (Gram path)
   const int64_t csz = precision == BIP_PREC_BF16 ? 4 : 8;  // bytes per complex element
@@ -496,9 +497,11 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   const int64_t esz = csz / planes;                         // bytes per plane element
   auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };   // padded window pixels
   auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };  // ... to whole tiles
-  // per-atom operand blocks (elements per plane), in buffer order
+  auto ldf_of = [](int W) { return roundup((int64_t)W * W, 64); };  // DFT workspace pitch
+  // per-atom blocks, in buffer order: [0] DFT workspace (complex64 elements),
+  // [1..3] contraction operands (plane elements)
   auto sizes = [&](int W, int64_t* s) {
-    s[0] = n1_of(W) * Bpad;                                        // S1~ [r][b]
+    s[0] = (int64_t)P * ldf_of(W);                                 // X [S_y][S_x][r]
     s[1] = gram ? n1_of(W) * Dk : Dpad * kd_of(W);                 // S2~^T [r][d] | S2~ [d][r]
     s[2] = gram ? n1_of(W) * kd_of(W) : (int64_t)n_ch * Ppad * kd_of(W);  // Q [r][r'] | U_n [rho][r]
     s[3] = gram ? Ppad * kd_of(W) : 0;                             // psi^T [rho][r]
@@ -506,18 +509,46 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   auto atom_bytes = [&](int a) {
     int64_t s[4];
     sizes(p->W[a], s);
-    return (s[0] + s[1] + s[2] + s[3]) * csz;
+    return s[0] * 8 + (s[1] + s[2] + s[3]) * csz;
   };
   int max_n1_all = 0;
   for (int a : atoms) max_n1_all = std::max<int>(max_n1_all, (int)n1_of(p->W[a]));
   const int64_t n_partial_tiles = gram ? max_n1_all / 128 : Dpad / 128;
+  // residue cells of the aperture beams (h_y mod S_y, h_x mod S_x), beams ascending in each
+  std::vector<int32_t>& cells = p->h_cells;
+  cells.assign((size_t)P + 1 + p->B, 0);
+  {
+    std::vector<int32_t> cell_of(p->B);
+    for (int b = 0; b < p->B; ++b) {
+      const int hy = p->beams[2 * b], hx = p->beams[2 * b + 1];
+      const int a = ((hy % scan_sy) + scan_sy) % scan_sy, c = ((hx % scan_sx) + scan_sx) % scan_sx;
+      cell_of[b] = a * scan_sx + c;
+      cells[cell_of[b] + 1]++;
+    }
+    for (int i = 0; i < P; ++i) cells[i + 1] += cells[i];
+    std::vector<int32_t> fill(cells.begin(), cells.begin() + P);
+    for (int b = 0; b < p->B; ++b) cells[P + 1 + fill[cell_of[b]]++] = b;
+  }
+  // twiddles exp(-2 pi i k / S) of the raster DFTs, rounded from double
+  std::vector<float2>& tws = p->h_tws;
+  tws.resize((size_t)scan_sx + scan_sy);
+  for (int k = 0; k < scan_sx; ++k) {
+    const double t = 2.0 * kPi * k / scan_sx;
+    tws[k] = make_float2((float)std::cos(t), (float)-std::sin(t));
+  }
+  for (int k = 0; k < scan_sy; ++k) {
+    const double t = 2.0 * kPi * k / scan_sy;
+    tws[scan_sx + k] = make_float2((float)std::cos(t), (float)-std::sin(t));
+  }
   const char* env = std::getenv("BIP_WORKSPACE_GB");
   const double budget_gb = env ? std::atof(env) : 24.0;
   const int64_t budget = (int64_t)(budget_gb * (1 << 30));
   const int64_t n_jobs_total = (int64_t)atoms.size() * (n_ch + 2);
-  const int64_t fixed = Ppad * Bpad * csz + n_partial_tiles * Ppad * 4 +
+  const int64_t fixed = n_partial_tiles * Ppad * 4 +
                         (out_mode == BIP_OUT_QEELS ? (int64_t)P * p->ndet * 4 : 0) +
-                        n_jobs_total * (int64_t)sizeof(GemmJob) + (1 << 20);
+                        n_jobs_total * (int64_t)sizeof(GemmJob) +
+                        (int64_t)atoms.size() * (int64_t)sizeof(ProbeJob) +
+                        (int64_t)cells.size() * 4 + (int64_t)tws.size() * 8 + (1 << 20);
   // chunking: consecutive atoms while the per-chunk operands fit the budget
   std::vector<std::pair<int, int>> chunks;
   int64_t max_chunk = 0;
@@ -538,7 +569,6 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   int rc = ensure_work(p, (size_t)(fixed + max_chunk + 16 * 256));
   if (rc) return rc;
   Workspace ws{(char*)p->d_work, 0};
-  void* Cm = ws.take(Ppad * Bpad * csz);
   float* partial = (float*)ws.take(n_partial_tiles * Ppad * 4);
   float* beams_out = out_mode == BIP_OUT_BEAMS ? out : nullptr;
   float* beams_tmp = nullptr;
@@ -547,17 +577,17 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     beams_out = beams_tmp;
   }
   GemmJob* d_jobs = (GemmJob*)ws.take(n_jobs_total * sizeof(GemmJob) + 64);
+  ProbeJob* d_probe = (ProbeJob*)ws.take(atoms.size() * sizeof(ProbeJob));
+  int32_t* d_cells = (int32_t*)ws.take(cells.size() * 4);
+  float2* d_tws = (float2*)ws.take(tws.size() * 8);
   const size_t chunk_base = ws.used;
-  const float cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
-  HIPCHK(timed(p, ST_ILLUM, st, [&] {
-           return launch_illumination(Cm, precision, Ppad * Bpad, (int)Bpad, (int)Ppad, p->d_beams,
-                                      p->B, scan_sy, scan_sx, cb, st);
-         }),
-         "illumination");
+  if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: tables exceed the workspace");
+  HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
+  HIPCHK(hipMemcpyAsync(d_tws, tws.data(), tws.size() * 8, hipMemcpyHostToDevice, st), "twiddles");
   if (out_mode == BIP_OUT_MAP || map_direct) HIPCHK(launch_zero(out, P, st), "zero");
   if (beams_out) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
-  // job tables, chunk-relative offsets; probe jobs, then contraction jobs, then map jobs
-  std::vector<GemmJob>& jprobe = p->h_jobs;
+  // job tables, chunk-relative offsets
+  std::vector<ProbeJob>& jprobe = p->h_probe;
   std::vector<GemmJob>& jdet = p->h_jobs2;
   std::vector<GemmJob>& jquad = p->h_jobs3;
   jprobe.clear();
@@ -583,20 +613,17 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     const int a = atoms[i];
     const int W = p->W[a];
     const int32_t W2 = W * W, kd = (int32_t)kd_of(W);
-    GemmJob j{};
-    // probe synthesis: A = illumination [rho][b], B = S1~ [r][b]
-    j.a_off = 0;
-    j.b_off = off[0][i];
-    j.K = (int32_t)Bpad;
-    j.lda = (int32_t)Bpad;
-    j.ldb = (int32_t)Bpad;
-    j.m_lim = (int32_t)Ppad;
-    j.n_lim = W2;
-    j.W2 = W2;
-    j.ldo = kd;
-    j.h_off = H_off[a];
-    j.out_off = gram ? off[3][i] : off[2][i];
-    jprobe.push_back(j);
+    ProbeJob pj{};
+    pj.win_off = p->off1[a];
+    pj.fx_off = off[0][i];
+    pj.out_off = gram ? off[3][i] : off[2][i];
+    pj.h_off = H_off[a];
+    pj.W = W;
+    pj.oy = p->oy[a];
+    pj.ox = p->ox[a];
+    pj.kd = kd;
+    pj.ldf = (int32_t)ldf_of(W);
+    jprobe.push_back(pj);
     det_first[i] = (int64_t)jdet.size();
     if (gram) {
       // Gram: A = B = S2~^T [r][d] (A conjugated), output Q [r][r']
@@ -632,23 +659,44 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       }
     }
   }
-  GemmJob* d_jprobe = d_jobs;
-  GemmJob* d_jdet = d_jprobe + jprobe.size();
+  GemmJob* d_jdet = d_jobs;
   GemmJob* d_jquad = d_jdet + jdet.size();
-  HIPCHK(hipMemcpyAsync(d_jprobe, jprobe.data(), jprobe.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
+  HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
   HIPCHK(hipMemcpyAsync(d_jdet, jdet.data(), jdet.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   if (!jquad.empty())
     HIPCHK(hipMemcpyAsync(d_jquad, jquad.data(), jquad.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
+  ProbeArgs pa{};
+  pa.win = p->d_win1;
+  pa.rowptr = p->d_rp1;
+  pa.col = p->d_col1;
+  pa.w = p->d_w1;
+  pa.beams = p->d_beams;
+  pa.cell_start = d_cells;
+  pa.cell_beams = d_cells + P + 1;
+  pa.twx = d_tws;
+  pa.twy = d_tws + scan_sx;
+  pa.tw = p->d_tw;
+  pa.L = p->L;
+  pa.ny = p->g.ny;
+  pa.nx = p->g.nx;
+  pa.mode = p->o.recon_mode;
+  pa.Sy = scan_sy;
+  pa.Sx = scan_sx;
+  pa.P = P;
+  pa.Ppad = (int)Ppad;
+  pa.cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
+  pa.H = (const float2*)H;
+  pa.n_ch = n_ch;
   for (size_t c = 0; c < chunks.size(); ++c) {
     ws.used = chunk_base;
     const int64_t pl0 = chunk_plane[0][c], pl1 = chunk_plane[1][c], pl2 = chunk_plane[2][c],
                   pl3 = chunk_plane[3][c];
-    char* S1op = (char*)ws.take(pl0 * csz);
+    float2* X = (float2*)ws.take(pl0 * 8);
     char* S2op = (char*)ws.take(pl1 * csz);
     char* X2 = (char*)ws.take(pl2 * csz);   // Q (Gram) or U (direct)
     char* PsiT = (char*)ws.take(std::max<int64_t>(pl3, 1) * csz);
     if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
-    int max_n1 = 0;
+    int max_n1 = 0, max_w2 = 0, max_kd = 0;
     const int c0 = chunks[c].first, c1 = chunks[c].second, nat = c1 - c0;
     for (int i = c0; i < c1; ++i) {
       const int a = atoms[i];
@@ -656,14 +704,11 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       int64_t s[4];
       sizes(W, s);
       max_n1 = std::max<int>(max_n1, (int)n1_of(W));
+      max_w2 = std::max(max_w2, W * W);
+      max_kd = std::max<int>(max_kd, (int)kd_of(W));
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
           off[3][i] + s[3] > pl3)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-      HIPCHK(timed(p, ST_RECON, st, [&] {
-               return launch_recon_operand(recon_args(p, a, 1), S1op + off[0][i] * esz, 0, precision,
-                                           Bpad, n1_of(W), Bpad, pl0, st);
-             }),
-             "recon S1 operand");
       if (gram)
         HIPCHK(timed(p, ST_RECON, st, [&] {
                  return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 0, precision,
@@ -677,26 +722,21 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
                }),
                "recon S2 operand");
     }
+    // probe synthesis for every atom of the chunk (grid z = atom)
+    pa.jobs = d_probe + c0;
+    pa.fx = X;
+    pa.out = gram ? (void*)PsiT : (void*)X2;
+    pa.out_plane = gram ? pl3 : pl2;
+    HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, max_w2, nat, st); }),
+           "probe fold");
+    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),
+           "probe synthesis");
     GemmArgs g{};
     g.H = (const float2*)H;
     g.n_ch = n_ch;
     g.ndet = p->ndet;
     g.P = P;
-    // probe synthesis for every atom of the chunk (grid z = atom)
-    g.A = Cm;
-    g.a_plane = Ppad * Bpad;
-    g.B = S1op;
-    g.b_plane = pl0;
-    g.jobs = d_jprobe + c0;
-    g.njobs = nat;
-    g.out = gram ? (void*)PsiT : (void*)X2;
-    g.out_plane = gram ? pl3 : pl2;
     g.Mpad = (int)Ppad;
-    HIPCHK(timed(p, ST_PROBE, st, [&] {
-             return launch_zgemm(precision, gram ? EPI_PSI : EPI_U, g, (int)(Ppad / 128), max_n1 / 128,
-                                 nat, st);
-           }),
-           "probe contraction");
     if (gram) {
       GemmArgs q = g;
       q.A = S2op;
@@ -719,7 +759,6 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       u.jobs = d_jquad + c0;
       u.njobs = nat;
       u.partial = partial;
-      u.Mpad = (int)Ppad;
       HIPCHK(timed(p, ST_DET, st, [&] {
                return launch_zgemm(precision, EPI_QUAD, u, (int)(Ppad / 128), max_n1 / 128, 1, st);
              }),

@@ -48,7 +48,7 @@ struct GemmJob {
   int32_t pad;
 };
 
-enum Epilogue { EPI_U = 0, EPI_PSI, EPI_ABS2_MAP, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD };
+enum Epilogue { EPI_ABS2_MAP = 0, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD };
 
 struct GemmArgs {
   const void* A;
@@ -58,13 +58,47 @@ struct GemmArgs {
   int njobs;
   void* out;                 // store epilogues
   int64_t out_plane;
-  const float2* H;           // transition potentials (EPI_U, EPI_GRAMQ)
+  const float2* H;           // transition potentials (EPI_GRAMQ)
   int n_ch;
   int Mpad, Npad;            // padded extents of the output (map partial pitches)
   float* partial;            // map partial sums
   float* out_beams;          // [P][ndet] (EPI_ABS2_BEAMS)
   int ndet, P;
 };
+// One atom of the probe synthesis (offsets in elements of their buffers).
+struct ProbeJob {
+  int64_t win_off;   // the atom's S1 parent windows [Bp1][W*W] in the window stack
+  int64_t fx_off;    // the atom's [S_y][S_x][ldf] block of the DFT workspace
+  int64_t out_off;   // the atom's operand block (plane elements)
+  int64_t h_off;     // first H element of the atom
+  int32_t W, oy, ox; // window
+  int32_t kd;        // row pitch of the operand (padded window pixels)
+  int32_t ldf;       // row pitch of the DFT workspace
+  int32_t pad;
+};
+
+struct ProbeArgs {
+  const ProbeJob* jobs;
+  const float2* win;        // S1 window stack
+  const int32_t* rowptr;    // CSR of w(1)
+  const int32_t* col;
+  const float* w;
+  const int2* beams;        // aperture beams [B]
+  const int32_t* cell_start;  // [S_y S_x + 1] beams of residue cell (a, c)
+  const int32_t* cell_beams;  // beam ids grouped by cell, ascending within a cell
+  const float2* twx;        // [S_x] exp(-2 pi i k / S_x)
+  const float2* twy;        // [S_y] exp(-2 pi i k / S_y)
+  const float2* tw;         // [L] exp(-2 pi i m / L)
+  int L, ny, nx, mode;
+  int Sy, Sx, P, Ppad;
+  float cb;                 // probe coefficient c_b
+  float2* fx;               // DFT workspace
+  void* out;                // operand planes
+  int64_t out_plane;
+  const float2* H;          // U_n = H_n psi when the detector contraction follows
+  int n_ch;
+};
+
 }  // namespace bip
 
 struct bip_plan {
@@ -106,9 +140,11 @@ struct bip_plan {
   void* d_work = nullptr;
   size_t work_bytes = 0;
   // host tables read by asynchronous copies; kept alive until the next call
-  std::vector<bip::GemmJob> h_jobs;
   std::vector<bip::GemmJob> h_jobs2, h_jobs3;
   std::vector<int32_t> h_qstart, h_qlist;
+  std::vector<bip::ProbeJob> h_probe;
+  std::vector<int32_t> h_cells;   // cell_start then cell_beams
+  std::vector<float2> h_tws;      // twx then twy
   std::vector<void*> allocations;
   // opt-in stage timing with HIP events on the caller's stream
   bool profiling = false;
@@ -122,7 +158,7 @@ struct bip_plan {
 namespace bip {
 
 enum Stage {
-  ST_TRANSMIT = 0, ST_S1_ROW, ST_S1_COL, ST_S2_ROW, ST_S2_COL, ST_INIT, ST_RECON, ST_ILLUM,
+  ST_TRANSMIT = 0, ST_S1_ROW, ST_S1_COL, ST_S2_ROW, ST_S2_COL, ST_INIT, ST_RECON, ST_FOLD,
   ST_PROBE, ST_DET, ST_REDUCE, ST_GRAM, ST_COUNT
 };
 
@@ -172,13 +208,17 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
                                 int64_t nrows_pad, int64_t ncols_pad, int64_t plane_stride,
                                 hipStream_t s);
 
+// probe synthesis (k_probe.hip); scan dimensions up to BIP_MAX_SCAN
+constexpr int BIP_MAX_SCAN = 256;
+size_t probe_lds_bytes(int S);
+hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipStream_t s);
+hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int n_jobs,
+                          hipStream_t s);
+
 // contraction (k_gemm.hip)
 hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n_tiles, int z,
                         hipStream_t s);
 int gemm_bk(int prec);
-// illumination matrix Cm [Ppad][Bpad] planes
-hipError_t launch_illumination(void* Cm, int prec, int64_t plane, int Bpad, int Ppad,
-                               const int2* beams, int B, int sy, int sx, float cb, hipStream_t s);
 hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,
                              int accumulate, hipStream_t s);
 hipError_t launch_qeels_from_beams(const float* beams_out, const int32_t* bin_start,

@@ -19,11 +19,9 @@
 // fragment load hit distinct banks.
 //
 // Roles (epilogues):
-//   EPI_U      probe synthesis psi^T[rho][r] = sum_b c_b(rho) S1~^b(r), written
-//              as U_n = H_n psi for every channel (operand of EPI_ABS2_*)
-//   EPI_PSI    probe synthesis written as psi^T itself (operand of EPI_QUAD)
 //   EPI_ABS2_MAP / EPI_ABS2_BEAMS
-//              a_d(rho) = sum_r S2~^d(r) U_n(r, rho); |a|^2 accumulated over
+//              a_d(rho) = sum_r S2~^d(r) U_n(r, rho), U_n = H_n psi from the
+//              probe synthesis; |a|^2 accumulated over
 //              the (atom, channel) jobs in registers, then summed over d (map)
 //              or added into [rho][d] (beams)
 //   EPI_GRAMQ  G[r][r'] = sum_d conj(S2~^d(r)) S2~^d(r') and its product with
@@ -33,6 +31,7 @@
 // For the map, sum_n sum_d |a_d|^2 = psi^H Q psi exactly, which replaces the
 // n_det x N_ch P detector contraction by a W^2 x W^2 Gram matrix per atom.
 #include "bip_internal.h"
+#include "planes.h"
 
 namespace bip {
 
@@ -70,13 +69,6 @@ constexpr int lds_bytes() {
 }
 
 __device__ inline int swz(int row) { return (row >> 2) & 3; }
-
-__device__ inline uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ inline v8bf neg8(v8bf a) {
   v4u u = __builtin_bit_cast(v4u, a);
@@ -253,41 +245,6 @@ __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t ld
   __syncthreads();
 }
 
-template <int PREC>
-__device__ inline void store_planes(void* out, int64_t idx, int64_t plane, float re, float im) {
-  if (PREC == BIP_PREC_FP32) {
-    float* o = (float*)out;
-    o[idx] = re;
-    o[idx + plane] = im;
-  } else if (PREC == BIP_PREC_SPLIT_BF16) {
-    uint16_t* o = (uint16_t*)out;
-    const uint16_t rh = f2bf(re), ih = f2bf(im);
-    o[idx] = rh;
-    o[idx + plane] = f2bf(re - bf2f(rh));
-    o[idx + 2 * plane] = ih;
-    o[idx + 3 * plane] = f2bf(im - bf2f(ih));
-  } else {
-    uint16_t* o = (uint16_t*)out;
-    o[idx] = f2bf(re);
-    o[idx + plane] = f2bf(im);
-  }
-}
-
-template <int PREC>
-__device__ inline float2 load_planes(const void* in, int64_t idx, int64_t plane) {
-  if (PREC == BIP_PREC_FP32) {
-    const float* o = (const float*)in;
-    return make_float2(o[idx], o[idx + plane]);
-  } else if (PREC == BIP_PREC_SPLIT_BF16) {
-    const uint16_t* o = (const uint16_t*)in;
-    return make_float2(bf2f(o[idx]) + bf2f(o[idx + plane]),
-                       bf2f(o[idx + 2 * plane]) + bf2f(o[idx + 3 * plane]));
-  } else {
-    const uint16_t* o = (const uint16_t*)in;
-    return make_float2(bf2f(o[idx]), bf2f(o[idx + plane]));
-  }
-}
-
 // ------------------------------------------------------------- the kernel
 template <int PREC, int EPI, bool CONJA>
 __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
@@ -341,7 +298,7 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
           }
       }
     } else {
-      // store epilogues: element (m, n) of this tile
+      // EPI_GRAMQ: element (m, n) = (r, r') of Q = G * sum_c conj(H_c(r)) H_c(r')
 #pragma unroll
       for (int bn = 0; bn < 4; ++bn) {
         const int n = n0 + wn * 64 + bn * 16 + lr;
@@ -352,37 +309,19 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
           for (int v = 0; v < 4; ++v) {
             const int m = m0 + wm * 64 + bm * 16 + kg * 4 + v;
             const float cr = acc.re[bm][bn][v], ci = acc.im[bm][bn][v];
-            if constexpr (EPI == EPI_PSI) {
-              const bool in = n < job.W2;
-              store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane,
-                                 in ? cr : 0.f, in ? ci : 0.f);
-            } else if constexpr (EPI == EPI_U) {
+            float qr = 0.f, qi = 0.f;
+            if (m < job.W2 && n < job.W2) {
+              float hr = 0.f, hi = 0.f;
               for (int c = 0; c < g.n_ch; ++c) {
-                float ur = 0.f, ui = 0.f;
-                if (n < job.W2) {
-                  const float2 h = g.H[job.h_off + (int64_t)c * job.W2 + n];
-                  ur = h.x * cr - h.y * ci;
-                  ui = h.x * ci + h.y * cr;
-                }
-                store_planes<PREC>(g.out, job.out_off + ((int64_t)c * g.Mpad + m) * job.ldo + n,
-                                   g.out_plane, ur, ui);
+                const float2 a = g.H[job.h_off + (int64_t)c * job.W2 + m];
+                const float2 b = g.H[job.h_off + (int64_t)c * job.W2 + n];
+                hr += a.x * b.x + a.y * b.y;
+                hi += a.x * b.y - a.y * b.x;
               }
-            } else {  // EPI_GRAMQ: m = r, n = r'; Q = G * sum_c conj(H_c(r)) H_c(r')
-              float qr = 0.f, qi = 0.f;
-              if (m < job.W2 && n < job.W2) {
-                float hr = 0.f, hi = 0.f;
-                for (int c = 0; c < g.n_ch; ++c) {
-                  const float2 a = g.H[job.h_off + (int64_t)c * job.W2 + m];
-                  const float2 b = g.H[job.h_off + (int64_t)c * job.W2 + n];
-                  hr += a.x * b.x + a.y * b.y;
-                  hi += a.x * b.y - a.y * b.x;
-                }
-                qr = cr * hr - ci * hi;
-                qi = cr * hi + ci * hr;
-              }
-              store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr,
-                                 qi);
+              qr = cr * hr - ci * hi;
+              qi = cr * hi + ci * hr;
             }
+            store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
           }
       }
     }
@@ -441,29 +380,6 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
 }
 
 // -------------------------------------------------------------- helpers
-template <int PREC>
-__global__ void k_illumination(void* Cm, int64_t plane, int Bpad, int Ppad,
-                               const int2* __restrict__ beams, int B, int sy, int sx, float cb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)Ppad * Bpad) return;
-  const int rho = (int)(i / Bpad);
-  const int b = (int)(i - (int64_t)rho * Bpad);
-  float re = 0.f, im = 0.f;
-  if (b < B && rho < sy * sx) {
-    const int u = rho / sx, v = rho - u * sx;
-    const int2 h = beams[b];
-    // exp(-2 pi i (h_y u / S_y + h_x v / S_x)) with an exact integer phase
-    const int64_t M = (int64_t)sy * sx;
-    int64_t m = ((int64_t)h.x * u * sx + (int64_t)h.y * v * sy) % M;
-    if (m < 0) m += M;
-    double s, c;
-    sincospi(-2.0 * (double)m / (double)M, &s, &c);
-    re = (float)(cb * c);
-    im = (float)(cb * s);
-  }
-  store_planes<PREC>(Cm, i, plane, re, im);
-}
-
 __global__ void k_reduce_map(const float* __restrict__ partial, int ntiles, int Ppad, int P,
                              float* out, int accumulate) {
   const int rho = blockIdx.x * blockDim.x + threadIdx.x;
@@ -499,8 +415,6 @@ hipError_t zgemm_launch(const GemmArgs& g, dim3 grid, hipStream_t s) {
 template <int PREC>
 hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
   switch (epi) {
-    case EPI_U: return zgemm_launch<PREC, EPI_U, false>(g, grid, s);
-    case EPI_PSI: return zgemm_launch<PREC, EPI_PSI, false>(g, grid, s);
     case EPI_ABS2_MAP: return zgemm_launch<PREC, EPI_ABS2_MAP, false>(g, grid, s);
     case EPI_ABS2_BEAMS: return zgemm_launch<PREC, EPI_ABS2_BEAMS, false>(g, grid, s);
     case EPI_GRAMQ: return zgemm_launch<PREC, EPI_GRAMQ, true>(g, grid, s);
@@ -524,29 +438,6 @@ hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n
 }
 
 int gemm_bk(int prec) { return prec == BIP_PREC_FP32 ? PT<BIP_PREC_FP32>::BK : 32; }
-
-hipError_t launch_illumination(void* Cm, int prec, int64_t plane, int Bpad, int Ppad,
-                               const int2* beams, int B, int sy, int sx, float cb, hipStream_t s) {
-  const int64_t n = (int64_t)Ppad * Bpad;
-  dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  switch (prec) {
-    case BIP_PREC_FP32:
-      hipLaunchKernelGGL(k_illumination<BIP_PREC_FP32>, grid, block, 0, s, Cm, plane, Bpad, Ppad,
-                         beams, B, sy, sx, cb);
-      break;
-    case BIP_PREC_SPLIT_BF16:
-      hipLaunchKernelGGL(k_illumination<BIP_PREC_SPLIT_BF16>, grid, block, 0, s, Cm, plane, Bpad,
-                         Ppad, beams, B, sy, sx, cb);
-      break;
-    case BIP_PREC_BF16:
-      hipLaunchKernelGGL(k_illumination<BIP_PREC_BF16>, grid, block, 0, s, Cm, plane, Bpad, Ppad,
-                         beams, B, sy, sx, cb);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,
                              int accumulate, hipStream_t s) {

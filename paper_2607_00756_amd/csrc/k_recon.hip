@@ -8,17 +8,11 @@
 // carrier exp(+/- 2 pi i h_b.r/N), whose phase index is exact integer
 // arithmetic on the absolute pixel.
 #include "bip_internal.h"
+#include "planes.h"
 
 namespace bip {
 
 namespace {
-
-__device__ inline uint16_t f2bf(float f) {  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ inline float2 recon_value(const ReconArgs& a, int b, int r) {
   const int W2 = a.W * a.W;
@@ -55,26 +49,6 @@ __global__ void k_recon_plain(ReconArgs a, float2* out) {
   out[i] = recon_value(a, b, r);
 }
 
-template <int PREC>
-__device__ inline void store_operand(void* out, int64_t idx, int64_t plane, float2 v) {
-  if (PREC == BIP_PREC_FP32) {
-    float* o = (float*)out;
-    o[idx] = v.x;
-    o[idx + plane] = v.y;
-  } else if (PREC == BIP_PREC_SPLIT_BF16) {
-    uint16_t* o = (uint16_t*)out;
-    const uint16_t rh = f2bf(v.x), ih = f2bf(v.y);
-    o[idx] = rh;
-    o[idx + plane] = f2bf(v.x - bf2f(rh));
-    o[idx + 2 * plane] = ih;
-    o[idx + 3 * plane] = f2bf(v.y - bf2f(ih));
-  } else {
-    uint16_t* o = (uint16_t*)out;
-    o[idx] = f2bf(v.x);
-    o[idx + plane] = f2bf(v.y);
-  }
-}
-
 // kind 0: element (r, b) at r*ld + b  (b fastest; S1~ as probe-GEMM operand)
 // kind 1: element (b, r) at b*ld + r  (r fastest; S2~ as detector-GEMM operand)
 template <int PREC, int KIND>
@@ -95,7 +69,7 @@ __global__ void k_recon_operand(ReconArgs a, void* out, int64_t ld, int64_t nrow
   }
   float2 v = make_float2(0.f, 0.f);
   if (b < a.nb && r < W2) v = recon_value(a, b, r);
-  store_operand<PREC>(out, row * ld + c, plane, v);
+  store_planes<PREC>(out, row * ld + c, plane, v.x, v.y);
 }
 
 }  // namespace
