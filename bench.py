@@ -47,7 +47,24 @@ def parse():
                     help="map through the per-beam detector contraction instead of the Gram form")
     ap.add_argument("--compare", action="store_true",
                     help="also time one step of the other precisions and report their error")
+    ap.add_argument("--column-batch", type=int, default=None,
+                    help="parent columns per sweep batch (sets BIP_COLUMN_BATCH; 0 = all)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times and exit: the known "
+                         "byte count that scales the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)  # one read and one write of n floats
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5,
+                                           "kernel": "torch elementwise mul (out=)"}}))
 
 
 def cpu_baseline(sp):
@@ -112,6 +129,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.column_batch is not None:
+        os.environ["BIP_COLUMN_BATCH"] = str(args.column_batch)
     import torch
     from paper_2607_00756_amd import bip, specimen
 

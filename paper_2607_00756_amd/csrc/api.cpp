@@ -216,6 +216,16 @@ int ensure_work(bip_plan* p, size_t bytes) {
   return BIP_OK;
 }
 
+// Parent columns per sweep batch: BIP_COLUMN_BATCH if set (0 = all columns),
+// else as many as fit in kColumnBatchBytes of state.
+constexpr int64_t kColumnBatchBytes = (int64_t)192 << 20;
+int column_batch(int64_t G) {
+  const char* env = std::getenv("BIP_COLUMN_BATCH");
+  int64_t b = env ? std::atoll(env) : kColumnBatchBytes / (G * 8);
+  if (b <= 0) b = INT32_MAX;
+  return (int)std::min<int64_t>(b, INT32_MAX);
+}
+
 GatherArgs gather_args(const bip_plan* p, int side) {
   GatherArgs g;
   g.plane_start = p->d_plane_start;
@@ -397,37 +407,49 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
   HIPCHK(timed(p, ST_TRANSMIT, st, [&] { return launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st); }), "transmit");
+  // Columns are advanced in batches, every slice of a batch before the next
+  // batch, so that a batch (both passes of every slice) can stay resident in
+  // the last-level cache; a batch of all columns is the plain slice-major sweep.
+  const int batch = column_batch(G);
   // ---- S1: entrance -> deepest ionization plane
   HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st); }),
          "init S1");
   GatherArgs g1 = gather_args(p, 1);
-  for (int j = 0; j <= p->i_max; ++j) {
-    int flags = ROW_GATHER_BEFORE_T;
-    if (j > 0) flags |= ROW_INV;
-    if (j < p->i_max) flags |= ROW_T | ROW_FWD;
-    HIPCHK(timed(p, ST_S1_ROW, st, [&] { return launch_row_pass(flags, p->d_state1, p->Bp1, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                           p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], st); }),
-           "S1 row pass");
-    if (j < p->i_max)
-      HIPCHK(timed(p, ST_S1_COL, st, [&] { return launch_col_pass(p->d_state1, p->Bp1, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
-             "S1 column pass");
+  for (int c0 = 0; c0 < p->Bp1; c0 += batch) {
+    const int nc = std::min(batch, p->Bp1 - c0);
+    float2* s1 = p->d_state1 + (int64_t)c0 * G;
+    for (int j = 0; j <= p->i_max; ++j) {
+      int flags = ROW_GATHER_BEFORE_T;
+      if (j > 0) flags |= ROW_INV;
+      if (j < p->i_max) flags |= ROW_T | ROW_FWD;
+      HIPCHK(timed(p, ST_S1_ROW, st, [&] { return launch_row_pass(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                             p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], c0, st); }),
+             "S1 row pass");
+      if (j < p->i_max)
+        HIPCHK(timed(p, ST_S1_COL, st, [&] { return launch_col_pass(s1, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
+               "S1 column pass");
+    }
   }
   // ---- S2: exit -> shallowest ionization plane (transpose multislice)
   HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
                                 (float)(1.0 / std::sqrt((double)G)), st); }),
          "init S2");
   GatherArgs g2 = gather_args(p, 2);
-  HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, p->d_state2, p->Bp2, g.ny, g.nx, nullptr, p->d_tw, p->L,
-                         p->d_par2, -1, g2, 0, 0, st); }),
-         "S2 row transform");
-  for (int j = g.nz - 1; j >= p->i_min; --j) {
-    HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(p->d_state2, p->Bp2, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
-           "S2 column pass");
-    int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
-    if (j > p->i_min) flags |= ROW_FWD;
-    HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, p->d_state2, p->Bp2, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                           p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], st); }),
-           "S2 row pass");
+  for (int c0 = 0; c0 < p->Bp2; c0 += batch) {
+    const int nc = std::min(batch, p->Bp2 - c0);
+    float2* s2 = p->d_state2 + (int64_t)c0 * G;
+    HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, s2, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
+                           p->d_par2, -1, g2, 0, 0, c0, st); }),
+           "S2 row transform");
+    for (int j = g.nz - 1; j >= p->i_min; --j) {
+      HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
+             "S2 column pass");
+      int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
+      if (j > p->i_min) flags |= ROW_FWD;
+      HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                             p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, st); }),
+             "S2 row pass");
+    }
   }
   p->built = true;
   return BIP_OK;
@@ -513,7 +535,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   };
   int max_n1_all = 0;
   for (int a : atoms) max_n1_all = std::max<int>(max_n1_all, (int)n1_of(p->W[a]));
-  const int64_t n_partial_tiles = gram ? max_n1_all / 128 : Dpad / 128;
+  const int64_t n_partial_tiles = gram ? GEMM_MAX_ZSPLIT * (max_n1_all / 128) : Dpad / 128;
   // residue cells of the aperture beams (h_y mod S_y, h_x mod S_x), beams ascending in each
   std::vector<int32_t>& cells = p->h_cells;
   cells.assign((size_t)P + 1 + p->B, 0);
@@ -747,8 +769,9 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       q.njobs = nat;
       q.out = X2;
       q.out_plane = pl2;
+      q.tiles = max_n1 / 128;
       HIPCHK(timed(p, ST_GRAM, st, [&] {
-               return launch_zgemm(precision, EPI_GRAMQ, q, max_n1 / 128, max_n1 / 128, nat, st);
+               return launch_zgemm(precision, EPI_GRAMQ, q, (int)gemm_gram_blocks(q.tiles, nat), 1, 1, st);
              }),
              "Gram contraction");
       GemmArgs u = g;
@@ -759,12 +782,15 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       u.jobs = d_jquad + c0;
       u.njobs = nat;
       u.partial = partial;
+      // enough job groups to fill the chip; partial rows reduced in a fixed order
+      const int qt = (int)(Ppad / 128) * (max_n1 / 128);
+      u.zsplit = std::max(1, std::min({GEMM_MAX_ZSPLIT, nat, (1024 + qt - 1) / qt}));
       HIPCHK(timed(p, ST_DET, st, [&] {
-               return launch_zgemm(precision, EPI_QUAD, u, (int)(Ppad / 128), max_n1 / 128, 1, st);
+               return launch_zgemm(precision, EPI_QUAD, u, (int)(Ppad / 128), max_n1 / 128, u.zsplit, st);
              }),
              "quadratic form");
       HIPCHK(timed(p, ST_REDUCE, st, [&] {
-               return launch_reduce_map(partial, max_n1 / 128, (int)Ppad, P, out, 1, st);
+               return launch_reduce_map(partial, u.zsplit * (max_n1 / 128), (int)Ppad, P, out, 1, st);
              }),
              "reduce");
     } else {

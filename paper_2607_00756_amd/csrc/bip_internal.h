@@ -64,6 +64,8 @@ struct GemmArgs {
   float* partial;            // map partial sums
   float* out_beams;          // [P][ndet] (EPI_ABS2_BEAMS)
   int ndet, P;
+  int tiles;                 // EPI_GRAMQ: 128-row tiles per side (upper triangle launched)
+  int zsplit;                // EPI_QUAD: job groups along grid z, one partial row each
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {
@@ -178,9 +180,10 @@ hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p,
 
 // multislice (k_multislice.hip)
 enum RowFlags { ROW_INV = 1, ROW_T = 2, ROW_FWD = 4, ROW_GATHER_BEFORE_T = 8, ROW_GATHER_AFTER_T = 16 };
+// state points at the first column of the batch; col0 is that column's parent index
 hipError_t launch_row_pass(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
                            const float2* tw, int L, const int2* parents, int detilt_sign,
-                           const GatherArgs& ga, int gather_begin, int gather_end,
+                           const GatherArgs& ga, int gather_begin, int gather_end, int col0,
                            hipStream_t s);
 hipError_t launch_col_pass(float2* state, int ncols, int ny, int nx, const float2* prop,
                            const float2* tw, int L, hipStream_t s);
@@ -216,8 +219,12 @@ hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int
                           hipStream_t s);
 
 // contraction (k_gemm.hip)
-hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n_tiles, int z,
+// grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit); for
+// EPI_GRAMQ a 1-D grid of gemm_gram_blocks(g.tiles, njobs) workgroups
+hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s);
+int64_t gemm_gram_blocks(int tiles, int njobs);
+constexpr int GEMM_MAX_ZSPLIT = 16;
 int gemm_bk(int prec);
 hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,
                              int accumulate, hipStream_t s);

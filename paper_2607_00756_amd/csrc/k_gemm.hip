@@ -254,11 +254,34 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, kg = lane >> 4;
-  // consecutive workgroups (dealt round-robin to the XCDs) take consecutive M
-  // tiles of one N tile
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int jb0 = ACCUM ? 0 : (int)blockIdx.z;
-  const int jb1 = ACCUM ? g.njobs : jb0 + 1;
+  int m0, n0, jb0, jb1;
+  if constexpr (EPI == EPI_GRAMQ) {
+    // 1-D grid.  Workgroup i runs on XCD i mod 8; all upper-triangle tiles of a
+    // job go to one XCD, so the job's operand rows are shared through its L2.
+    const int nt = g.tiles, T = nt * (nt + 1) / 2;
+    const int slot = (int)(blockIdx.x >> 3);
+    jb0 = (slot / T) * 8 + (int)(blockIdx.x & 7);
+    if (jb0 >= g.njobs) return;  // uniform per workgroup
+    jb1 = jb0 + 1;
+    int tl = slot % T, ti = 0;
+    while (tl >= nt - ti) {
+      tl -= nt - ti;
+      ++ti;
+    }
+    m0 = ti * BM;
+    n0 = (ti + tl) * BN;
+  } else {
+    // consecutive workgroups take consecutive M tiles of one N tile
+    m0 = blockIdx.x * BM;
+    n0 = blockIdx.y * BN;
+    if constexpr (EPI == EPI_QUAD) {  // job group z of g.zsplit
+      jb0 = (int)((int64_t)g.njobs * blockIdx.z / g.zsplit);
+      jb1 = (int)((int64_t)g.njobs * (blockIdx.z + 1) / g.zsplit);
+    } else {
+      jb0 = 0;
+      jb1 = g.njobs;
+    }
+  }
   v4f sq[4][4];
   if constexpr (ACCUM) {
 #pragma unroll
@@ -322,6 +345,10 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
               qi = cr * hi + ci * hr;
             }
             store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
+            // Q is Hermitian: the tile below the diagonal is the conjugate transpose
+            if (m0 != n0 && m < job.ldo)
+              store_planes<PREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
+                                 -qi);
           }
       }
     }
@@ -361,7 +388,9 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
           if (lr == 0) red[wn][wm * 64 + bm * 16 + kg * 4 + v] = s;
         }
       __syncthreads();
-      if (tid < BM) g.partial[(int64_t)blockIdx.y * g.Mpad + m0 + tid] = red[0][tid] + red[1][tid];
+      if (tid < BM)
+        g.partial[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * g.Mpad + m0 + tid] =
+            red[0][tid] + red[1][tid];
     }
   } else if constexpr (EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
@@ -425,16 +454,23 @@ hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int m_tiles, int n_tiles, int z,
+hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s) {
-  if (m_tiles <= 0 || n_tiles <= 0 || z <= 0 || g.njobs <= 0) return hipSuccess;
-  const dim3 grid(m_tiles, n_tiles, z);
+  if (gx <= 0 || gy <= 0 || gz <= 0 || g.njobs <= 0) return hipSuccess;
+  if (epi == EPI_QUAD && (g.zsplit != gz || gz > g.njobs)) return hipErrorInvalidValue;
+  if (epi == EPI_GRAMQ && (g.tiles <= 0 || gx != gemm_gram_blocks(g.tiles, g.njobs) || gy != 1 || gz != 1))
+    return hipErrorInvalidValue;
+  const dim3 grid(gx, gy, gz);
   switch (prec) {
     case BIP_PREC_FP32: return zgemm_prec<BIP_PREC_FP32>(epi, g, grid, s);
     case BIP_PREC_SPLIT_BF16: return zgemm_prec<BIP_PREC_SPLIT_BF16>(epi, g, grid, s);
     case BIP_PREC_BF16: return zgemm_prec<BIP_PREC_BF16>(epi, g, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+int64_t gemm_gram_blocks(int tiles, int njobs) {
+  return 8 * (int64_t)((njobs + 7) / 8) * (tiles * (tiles + 1) / 2);
 }
 
 int gemm_bk(int prec) { return prec == BIP_PREC_FP32 ? PT<BIP_PREC_FP32>::BK : 32; }

@@ -59,13 +59,14 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
                                                   const float2* __restrict__ T,
                                                   const float2* __restrict__ tw, int L,
                                                   const int2* __restrict__ parents, int sign,
-                                                  GatherArgs ga, int gb, int ge) {
+                                                  GatherArgs ga, int gb, int ge, int col0) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
   const int t = threadIdx.x % S::T;
   const int f = threadIdx.x / S::T;
   const int y = blockIdx.x * S::ROWS + f;
-  const int col = blockIdx.y;
+  const int col = blockIdx.y;   // column of this launch's batch
+  const int pcol = col0 + col;  // parent index
   float2* row = state + ((int64_t)col * ny + y) * NX;
   float2* my_lds = lds + f * S::LDS_ROW;
   float2 v[16];
@@ -73,14 +74,14 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
   for (int e = 0; e < 16; ++e) v[e] = row[t + S::T * e];
   if (FLAGS & ROW_INV) fft::transform<NX, true, 1, true>(v, my_lds, t, tw, L);
   if ((FLAGS & ROW_GATHER_BEFORE_T) && ge > gb)
-    gather_row<NX>(v, t, y, col, ny, ga, gb, ge, parents[col], tw, L, sign);
+    gather_row<NX>(v, t, y, pcol, ny, ga, gb, ge, parents[pcol], tw, L, sign);
   if (FLAGS & ROW_T) {
     const float2* Trow = T + (int64_t)y * NX;
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], Trow[t + S::T * e]);
   }
   if ((FLAGS & ROW_GATHER_AFTER_T) && ge > gb)
-    gather_row<NX>(v, t, y, col, ny, ga, gb, ge, parents[col], tw, L, sign);
+    gather_row<NX>(v, t, y, pcol, ny, ga, gb, ge, parents[pcol], tw, L, sign);
   if (FLAGS & ROW_FWD) {
     fft::transform<NX, false, 1, true>(v, my_lds, t, tw, L);
 #pragma unroll
@@ -120,21 +121,21 @@ __global__ __launch_bounds__(ColShape<NY>::THREADS) void k_col_pass(
 template <int NX, int FLAGS>
 hipError_t row_launch(float2* state, int ncols, int ny, const float2* T, const float2* tw, int L,
                       const int2* parents, int sign, const GatherArgs& ga, int gb, int ge,
-                      hipStream_t s) {
+                      int col0, hipStream_t s) {
   using S = RowShape<NX>;
   dim3 grid(ny / S::ROWS, ncols);
   hipLaunchKernelGGL((k_row_pass<NX, FLAGS>), grid, dim3(256), 0, s, state, ny, T, tw, L, parents,
-                     sign, ga, gb, ge);
+                     sign, ga, gb, ge, col0);
   return hipGetLastError();
 }
 
 template <int NX>
 hipError_t row_dispatch(int flags, float2* state, int ncols, int ny, const float2* T,
                         const float2* tw, int L, const int2* parents, int sign,
-                        const GatherArgs& ga, int gb, int ge, hipStream_t s) {
+                        const GatherArgs& ga, int gb, int ge, int col0, hipStream_t s) {
 #define ROW_CASE(F) \
   case F:           \
-    return row_launch<NX, F>(state, ncols, ny, T, tw, L, parents, sign, ga, gb, ge, s);
+    return row_launch<NX, F>(state, ncols, ny, T, tw, L, parents, sign, ga, gb, ge, col0, s);
   switch (flags) {
     ROW_CASE(ROW_GATHER_BEFORE_T | ROW_T | ROW_FWD)
     ROW_CASE(ROW_INV | ROW_GATHER_BEFORE_T | ROW_T | ROW_FWD)
@@ -154,15 +155,15 @@ hipError_t row_dispatch(int flags, float2* state, int ncols, int ny, const float
 
 hipError_t launch_row_pass(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
                            const float2* tw, int L, const int2* parents, int detilt_sign,
-                           const GatherArgs& ga, int gather_begin, int gather_end,
+                           const GatherArgs& ga, int gather_begin, int gather_end, int col0,
                            hipStream_t s) {
   if (ncols == 0) return hipSuccess;
   switch (nx) {
-    case 64: return row_dispatch<64>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
-    case 128: return row_dispatch<128>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
-    case 256: return row_dispatch<256>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
-    case 512: return row_dispatch<512>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
-    case 1024: return row_dispatch<1024>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, s);
+    case 64: return row_dispatch<64>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, col0, s);
+    case 128: return row_dispatch<128>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, col0, s);
+    case 256: return row_dispatch<256>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, col0, s);
+    case 512: return row_dispatch<512>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, col0, s);
+    case 1024: return row_dispatch<1024>(flags, state, ncols, ny, T, tw, L, parents, detilt_sign, ga, gather_begin, gather_end, col0, s);
     default: return hipErrorInvalidValue;
   }
 }
