@@ -193,9 +193,13 @@ def main():
     else:
         work["gram_gemm"] = (float(np.sum(8.0 * W2 * W2 * nd)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
         work["det_gemm"] = (float(np.sum(8.0 * W2 * W2 * P)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
-    # parent sweeps: every pass reads and writes the whole state of its columns
+    # parent sweeps: every pass reads and writes the whole state of the columns
+    # of its batch; launches_per_step / n_batches passes over all columns
+    batch = int(plan.query(bip.Q_SCALARS)[2])
     for st, ncol in (("s1_row", plan.Bp1), ("s1_col", plan.Bp1), ("s2_row", plan.Bp2), ("s2_col", plan.Bp2)):
-        work[st] = (16.0 * G * ncol * stages[st][1] / args.steps / 1e9, "GB/s", "hbm", HBM_PEAK_GBS)
+        n_batches = -(-ncol // batch)
+        work[st] = (16.0 * G * ncol * stages[st][1] / args.steps / n_batches / 1e9, "GB/s", "hbm",
+                    HBM_PEAK_GBS)
     names = {"probe_fold": "k_probe_fold_x (S1~ reconstruction + residue fold + DFT over x)",
              "probe_dft": "k_probe_y (DFT over y, operand store)",
              "recon": "k_recon_operand (S2~ reconstruction)",
@@ -232,7 +236,8 @@ def main():
                                f"scan {cfg.scan[0]}x{cfg.scan[1]}, map",
                    "units_per_step": units, "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1,
                    "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision,
-                   "map_contraction": "direct" if args.map_direct else "gram"},
+                   "map_contraction": "direct" if args.map_direct else "gram",
+                   "column_batch": int(plan.query(bip.Q_SCALARS)[2])},
         "roofline": {"bound": bound, "kernel": names[dom], "stage": dom,
                      "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                      "traffic": None, "launches_per_step": launches_per_step,

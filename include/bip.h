@@ -169,7 +169,8 @@ enum {
   BIP_Q_WEIGHTS1 = 6, /* CSR of w(1): i32 rowptr[B+1], i32 col[nnz1], f64 w[nnz1] packed
                          back to back in that order (host buffer)             */
   BIP_Q_WEIGHTS2 = 7, /* same for the detector weights w(2)                   */
-  BIP_Q_SCALARS = 8   /* f64[4]: lambda (A), sigma (rad/(V A)), 0, 0          */
+  BIP_Q_SCALARS = 8   /* f64[4]: lambda (A), sigma (rad/(V A)), parent columns per
+                         sweep batch of the last bip_build_smatrix (0 before), 0 */
 };
 
 /* bip_query -- copy plan metadata into the host buffer `out`. */

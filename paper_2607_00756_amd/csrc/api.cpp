@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "bip_internal.h"
+#include "recon_core.h"
 
 namespace bip {
 
@@ -244,6 +245,8 @@ ReconArgs recon_args(const bip_plan* p, int a, int side) {
   r.rowptr = side == 1 ? p->d_rp1 : p->d_rp2;
   r.col = side == 1 ? p->d_col1 : p->d_col2;
   r.w = side == 1 ? p->d_w1 : p->d_w2;
+  r.ellc = side == 1 ? p->d_ellc1 : p->d_ellc2;
+  r.ellw = side == 1 ? p->d_ellw1 : p->d_ellw2;
   r.beams = side == 1 ? p->d_beams : p->d_det;
   r.nb = side == 1 ? p->B : p->ndet;
   r.W = p->W[a];
@@ -374,6 +377,26 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     return r;
   };
   std::vector<float> w1f(p->w1.begin(), p->w1.end()), w2f(p->w2.begin(), p->w2.end());
+  // padded copies of the CSR rows: six (parent, weight) slots, row length, row start
+  auto ell = [](const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
+                const std::vector<double>& w, std::vector<int32_t>& ec, std::vector<float>& ew) {
+    const int nb = (int)rp.size() - 1;
+    ec.assign((size_t)nb * ELL_W, 0);
+    ew.assign((size_t)nb * ELL_W, 0.f);
+    for (int b = 0; b < nb; ++b) {
+      const int lo = rp[b], n = rp[b + 1] - lo;
+      for (int j = 0; j < std::min(n, ELL_K); ++j) {
+        ec[(size_t)b * ELL_W + j] = cl[lo + j];
+        ew[(size_t)b * ELL_W + j] = (float)w[lo + j];
+      }
+      ec[(size_t)b * ELL_W + 6] = n;
+      ec[(size_t)b * ELL_W + 7] = lo;
+    }
+  };
+  std::vector<int32_t> ec1, ec2;
+  std::vector<float> ew1, ew2;
+  ell(p->rp1, p->col1, p->w1, ec1, ew1);
+  ell(p->rp2, p->col2, p->w2, ec2, ew2);
   if ((rc = dalloc(p, &p->d_tw, p->L)) || (rc = dalloc(p, &p->d_prop, G)) ||
       (rc = dalloc(p, &p->d_T, G * g.nz)) || (rc = upload(p, &p->d_beams, as_int2(p->beams), st)) ||
       (rc = upload(p, &p->d_det, as_int2(p->det), st)) ||
@@ -382,6 +405,8 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = upload(p, &p->d_rp1, p->rp1, st)) || (rc = upload(p, &p->d_col1, p->col1, st)) ||
       (rc = upload(p, &p->d_w1, w1f, st)) || (rc = upload(p, &p->d_rp2, p->rp2, st)) ||
       (rc = upload(p, &p->d_col2, p->col2, st)) || (rc = upload(p, &p->d_w2, w2f, st)) ||
+      (rc = upload(p, &p->d_ellc1, ec1, st)) || (rc = upload(p, &p->d_ellw1, ew1, st)) ||
+      (rc = upload(p, &p->d_ellc2, ec2, st)) || (rc = upload(p, &p->d_ellw2, ew2, st)) ||
       (rc = upload(p, &p->d_W, p->W, st)) || (rc = upload(p, &p->d_oy, p->oy, st)) ||
       (rc = upload(p, &p->d_ox, p->ox, st)) || (rc = upload(p, &p->d_off1, p->off1, st)) ||
       (rc = upload(p, &p->d_off2, p->off2, st)) ||
@@ -411,6 +436,7 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   // batch, so that a batch (both passes of every slice) can stay resident in
   // the last-level cache; a batch of all columns is the plain slice-major sweep.
   const int batch = column_batch(G);
+  p->column_batch = batch;
   // ---- S1: entrance -> deepest ionization plane
   HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st); }),
          "init S1");
@@ -692,6 +718,8 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   pa.rowptr = p->d_rp1;
   pa.col = p->d_col1;
   pa.w = p->d_w1;
+  pa.ellc = p->d_ellc1;
+  pa.ellw = p->d_ellw1;
   pa.beams = p->d_beams;
   pa.cell_start = d_cells;
   pa.cell_beams = d_cells + P + 1;
@@ -900,7 +928,7 @@ int bip_query(const bip_plan* p, int32_t what, void* out) {
       double* o = (double*)out;
       o[0] = p->lambda;
       o[1] = p->sigma;
-      o[2] = 0;
+      o[2] = p->column_batch;
       o[3] = 0;
       return BIP_OK;
     }

@@ -85,6 +85,8 @@ struct ProbeArgs {
   const int32_t* rowptr;    // CSR of w(1)
   const int32_t* col;
   const float* w;
+  const int32_t* ellc;      // padded rows of w(1) [B][8]
+  const float* ellw;
   const int2* beams;        // aperture beams [B]
   const int32_t* cell_start;  // [S_y S_x + 1] beams of residue cell (a, c)
   const int32_t* cell_beams;  // beam ids grouped by cell, ascending within a cell
@@ -120,6 +122,7 @@ struct bip_plan {
   std::vector<int32_t> plane_start, plane_atoms;
   int i_min = 0, i_max = 0;
   bool built = false;
+  int column_batch = 0;  // parent columns per sweep batch of the last build
   // device buffers
   float2* d_tw = nullptr;       // [L] exp(-2 pi i m / L)
   float2* d_prop = nullptr;     // [ny][nx] P(q) / G
@@ -130,6 +133,8 @@ struct bip_plan {
   int2* d_par2 = nullptr;       // [Bp2]
   int32_t *d_rp1 = nullptr, *d_col1 = nullptr, *d_rp2 = nullptr, *d_col2 = nullptr;
   float *d_w1 = nullptr, *d_w2 = nullptr;
+  int32_t *d_ellc1 = nullptr, *d_ellc2 = nullptr;  // padded CSR rows
+  float *d_ellw1 = nullptr, *d_ellw2 = nullptr;
   int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
   int64_t *d_off1 = nullptr, *d_off2 = nullptr;
   int32_t *d_plane_start = nullptr, *d_plane_atoms = nullptr;
@@ -194,6 +199,8 @@ struct ReconArgs {
   const int32_t* rowptr; // CSR of the weights
   const int32_t* col;
   const float* w;
+  const int32_t* ellc;   // padded rows of the CSR [nb][8] (parents, length, start)
+  const float* ellw;     // padded weights [nb][8]
   const int2* beams;     // target beams [nb]
   int nb;                // number of target beams
   int W, oy, ox;         // window

@@ -23,6 +23,7 @@
 // Both DFTs run in FP32 on the vector ALUs with twiddles rounded from FP64.
 #include "bip_internal.h"
 #include "planes.h"
+#include "recon_core.h"
 
 namespace bip {
 
@@ -85,24 +86,11 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
     float2 F = make_float2(0.f, 0.f);
     for (int k = pa.cell_start[cell]; k < k1; ++k) {
       const int b = pa.cell_beams[k];
-      float2 z = make_float2(0.f, 0.f);
-      float m = 0.f;
-      const int j1 = pa.rowptr[b + 1];
-      for (int j = pa.rowptr[b]; j < j1; ++j) {
-        const float2 D = win[(int64_t)pa.col[j] * W2 + rr];
-        const float w = pa.w[j];
-        z.x += w * D.x;
-        z.y += w * D.y;
-        m += w * sqrtf(D.x * D.x + D.y * D.y);
-      }
-      float2 s = z;
-      if (pa.mode == BIP_RECON_MAGNITUDE) {
-        const float az = sqrtf(z.x * z.x + z.y * z.y);
-        s = az > 0.f ? cscale(z, m / az) : make_float2(0.f, 0.f);
-      }
       const int2 h = pa.beams[b];
       const float2 t = pa.tw[(h.x * py + h.y * px) & (pa.L - 1)];  // exp(-2 pi i h.r/N)
-      F = cadd(F, cmulc(s, t));                                    // re-tilt by exp(+...)
+      const float2 s = recon_combine(win, W2, rr, pa.ellc + (int64_t)b * ELL_W,
+                                     pa.ellw + (int64_t)b * ELL_W, pa.col, pa.w, pa.mode);
+      F = cadd(F, cmulc(s, t));  // re-tilt by exp(+2 pi i h.r/N)
     }
     sF[c * RT + lane] = live ? F : make_float2(0.f, 0.f);
   }

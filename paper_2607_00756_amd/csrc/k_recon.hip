@@ -9,6 +9,7 @@
 // arithmetic on the absolute pixel.
 #include "bip_internal.h"
 #include "planes.h"
+#include "recon_core.h"
 
 namespace bip {
 
@@ -49,24 +50,25 @@ __global__ void k_recon_plain(ReconArgs a, float2* out) {
   out[i] = recon_value(a, b, r);
 }
 
-// GEMM operand output, one 64-beam x 64-pixel tile per workgroup.
+// GEMM operand output, one 64-beam x 32-pixel tile per workgroup.
 // kind 0: element (r, b) at r*ld + b  (b fastest; S2~^T for the Gram matrix)
 // kind 1: element (b, r) at b*ld + r  (r fastest; S2~ for the detector contraction)
-// Values are computed with lanes running over consecutive pixels, so every
-// parent read is a coalesced 512-byte row segment; the weights of the tile's
-// beams are staged in LDS first so that all parent reads of a value are in
-// flight together.  Kind 0 transposes through LDS before the store.
-// Rows and columns beyond the beams or the window are written as zeros.
-constexpr int TB = 64, TR = 64, KMAX = 8;
+// Each half-wave computes one beam on 32 consecutive pixels, so every parent
+// read is a coalesced 256-byte row segment; the padded weight rows of the
+// tile's beams are staged in LDS first and the parent reads of a value are
+// issued together.  Kind 0 transposes through LDS so that each stored row holds
+// 64 consecutive beams.  The small LDS footprint (~21 KB) keeps 7 workgroups
+// per CU resident to hide the read latency.  Rows and columns beyond the beams
+// or the window are written as zeros.
+constexpr int TB = 64, TR = 32;
 
 template <int PREC, int KIND>
 __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, int64_t ld,
                                                        int nrows, int ncols, int64_t plane) {
   __shared__ float2 tile[TB][TR + 1];
-  __shared__ float2 stw[1024];
-  __shared__ int s_lo[TB], s_cnt[TB];
-  __shared__ int s_col[TB][KMAX];
-  __shared__ float s_w[TB][KMAX];
+  __shared__ int s_ec[TB][ELL_W];
+  __shared__ float s_ew[TB][ELL_W];
+  __shared__ int2 s_h[TB];
   const int n_b = KIND == 0 ? ncols : nrows;  // beams to write (padded)
   const int n_r = KIND == 0 ? nrows : ncols;  // pixels to write (padded)
   const int nbt = (n_b + TB - 1) / TB, nrt = (n_r + TR - 1) / TR;
@@ -76,27 +78,19 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
   const int per = (int)(gridDim.x / 8);
   const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
   if (t >= nt) return;
-  for (int i = threadIdx.x; i < a.L; i += 256) stw[i] = a.tw[i];
   const int b0 = (t / nrt) * TB, r0 = (t % nrt) * TR;
-  // the weights of the tile's beams (first KMAX of each row) go to LDS
-  if (threadIdx.x < TB) {
-    const int b = b0 + threadIdx.x;
-    int lo = 0, cnt = 0;
-    if (b < a.nb) {
-      lo = a.rowptr[b];
-      cnt = a.rowptr[b + 1] - lo;
-    }
-    s_lo[threadIdx.x] = lo;
-    s_cnt[threadIdx.x] = cnt;
-    for (int j = 0; j < KMAX; ++j) {
-      s_col[threadIdx.x][j] = j < cnt ? a.col[lo + j] : 0;
-      s_w[threadIdx.x][j] = j < cnt ? a.w[lo + j] : 0.f;
-    }
+  for (int i = threadIdx.x; i < TB * ELL_W; i += 256) {
+    const int bl = i / ELL_W, j = i % ELL_W;
+    const bool in = b0 + bl < a.nb;
+    s_ec[bl][j] = in ? a.ellc[(int64_t)(b0 + bl) * ELL_W + j] : 0;
+    s_ew[bl][j] = in ? a.ellw[(int64_t)(b0 + bl) * ELL_W + j] : 0.f;
   }
+  if (threadIdx.x < TB) s_h[threadIdx.x] = b0 + (int)threadIdx.x < a.nb ? a.beams[b0 + threadIdx.x] : make_int2(0, 0);
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = threadIdx.x >> 6;
+  const int half = lane >> 5, px32 = lane & 31;
   const int W2 = a.W * a.W;
-  const int r = r0 + lane;
+  const int r = r0 + px32;
   const bool live = r < W2;
   const int rr = live ? r : 0;
   const int ry = rr / a.W, rx = rr - ry * a.W;
@@ -104,58 +98,34 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
   const int px = ((a.ox + rx) & (a.nx - 1)) * (a.L / a.nx);
   __syncthreads();
 #pragma unroll 2
-  for (int k = 0; k < TB / 4; ++k) {
-    const int bl = wave + 4 * k;
-    const int b = b0 + bl;  // wave-uniform
+  for (int k = 0; k < TB / 8; ++k) {
+    const int bl = 2 * wave + half + 8 * k;
+    const int b = b0 + bl;
     float2 v = make_float2(0.f, 0.f);
-    if (b < a.nb) {
-      const int cnt = s_cnt[bl];
-      float2 D[KMAX];
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < cnt) D[j] = a.win[(int64_t)s_col[bl][j] * W2 + rr];
-      float2 z = make_float2(0.f, 0.f);
-      float m = 0.f;
-#pragma unroll
-      for (int j = 0; j < KMAX; ++j)
-        if (j < cnt) {
-          const float w = s_w[bl][j];
-          z.x += w * D[j].x;
-          z.y += w * D[j].y;
-          m += w * sqrtf(D[j].x * D[j].x + D[j].y * D[j].y);
-        }
-      for (int j = s_lo[bl] + KMAX; j < s_lo[bl] + cnt; ++j) {  // rows longer than KMAX
-        const float2 Dj = a.win[(int64_t)a.col[j] * W2 + rr];
-        const float w = a.w[j];
-        z.x += w * Dj.x;
-        z.y += w * Dj.y;
-        m += w * sqrtf(Dj.x * Dj.x + Dj.y * Dj.y);
-      }
-      float2 s = z;
-      if (a.mode == BIP_RECON_MAGNITUDE) {
-        const float az = sqrtf(z.x * z.x + z.y * z.y);
-        s = az > 0.f ? cscale(z, m / az) : make_float2(0.f, 0.f);
-      }
-      const int2 h = a.beams[b];
-      const float2 tw = stw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
-      v = a.retilt_sign > 0 ? cmulc(s, tw) : cmul(s, tw);
-      if (!live) v = make_float2(0.f, 0.f);
-    }
-    tile[bl][lane] = v;
+    const int2 h = s_h[bl];
+    const float2 tw = a.tw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
+    const float2 s = recon_combine(a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
+    if (b < a.nb && live) v = a.retilt_sign > 0 ? cmulc(s, tw) : cmul(s, tw);
+    tile[bl][px32] = v;
   }
   __syncthreads();
-  for (int k = 0; k < TB / 4; ++k) {
-    const int j = wave + 4 * k;
-    if (KIND == 0) {  // row r0 + j, beams b0 + lane
+  if (KIND == 0) {  // rows r0 + j (8 per wave), 64 consecutive beams per row
+#pragma unroll 2
+    for (int k = 0; k < TR / 4; ++k) {
+      const int j = wave + 4 * k;
       const int ro = r0 + j, bo = b0 + lane;
       if (ro < n_r && bo < n_b) {
         const float2 v = tile[lane][j];
         store_planes<PREC>(out, (int64_t)ro * ld + bo, plane, v.x, v.y);
       }
-    } else {  // row b0 + j, pixels r0 + lane
-      const int bo = b0 + j, ro = r0 + lane;
+    }
+  } else {  // rows b0 + j, 32 consecutive pixels per half-wave
+#pragma unroll 2
+    for (int k = 0; k < TB / 8; ++k) {
+      const int j = 2 * wave + half + 8 * k;
+      const int bo = b0 + j, ro = r0 + px32;
       if (bo < n_b && ro < n_r) {
-        const float2 v = tile[j][lane];
+        const float2 v = tile[j][px32];
         store_planes<PREC>(out, (int64_t)bo * ld + ro, plane, v.x, v.y);
       }
     }
@@ -175,7 +145,7 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
                                 int64_t nrows_pad, int64_t ncols_pad, int64_t plane_stride,
                                 hipStream_t s) {
   if (nrows_pad <= 0 || ncols_pad <= 0) return hipSuccess;
-  if (a.L > 1024 || nrows_pad > INT32_MAX || ncols_pad > INT32_MAX) return hipErrorInvalidValue;
+  if (nrows_pad > INT32_MAX || ncols_pad > INT32_MAX) return hipErrorInvalidValue;
   const int64_t n_b = kind == 0 ? ncols_pad : nrows_pad, n_r = kind == 0 ? nrows_pad : ncols_pad;
   const int64_t nt = ((n_b + TB - 1) / TB) * ((n_r + TR - 1) / TR);
   const int64_t nblk = (nt + 7) / 8 * 8;
