@@ -229,12 +229,7 @@ int column_batch(int64_t G) {
 
 GatherArgs gather_args(const bip_plan* p, int side) {
   GatherArgs g;
-  g.plane_start = p->d_plane_start;
-  g.plane_atoms = p->d_plane_atoms;
-  g.W = p->d_W;
-  g.oy = p->d_oy;
-  g.ox = p->d_ox;
-  g.off = side == 1 ? p->d_off1 : p->d_off2;
+  g.rec = side == 1 ? p->d_grec1 : p->d_grec2;
   g.win = side == 1 ? p->d_win1 : p->d_win2;
   return g;
 }
@@ -377,6 +372,12 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     return r;
   };
   std::vector<float> w1f(p->w1.begin(), p->w1.end()), w2f(p->w2.begin(), p->w2.end());
+  std::vector<GatherRec> grec1(n_atoms), grec2(n_atoms);
+  for (int q = 0; q < n_atoms; ++q) {
+    const int a = p->plane_atoms[q];
+    grec1[q] = GatherRec{p->W[a], p->oy[a], p->ox[a], 0, p->off1[a]};
+    grec2[q] = GatherRec{p->W[a], p->oy[a], p->ox[a], 0, p->off2[a]};
+  }
   // padded copies of the CSR rows: six (parent, weight) slots, row length, row start
   auto ell = [](const std::vector<int32_t>& rp, const std::vector<int32_t>& cl,
                 const std::vector<double>& w, std::vector<int32_t>& ec, std::vector<float>& ew) {
@@ -410,8 +411,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = upload(p, &p->d_W, p->W, st)) || (rc = upload(p, &p->d_oy, p->oy, st)) ||
       (rc = upload(p, &p->d_ox, p->ox, st)) || (rc = upload(p, &p->d_off1, p->off1, st)) ||
       (rc = upload(p, &p->d_off2, p->off2, st)) ||
-      (rc = upload(p, &p->d_plane_start, p->plane_start, st)) ||
-      (rc = upload(p, &p->d_plane_atoms, p->plane_atoms, st)) ||
+      (rc = upload(p, &p->d_grec1, grec1, st)) || (rc = upload(p, &p->d_grec2, grec2, st)) ||
       (rc = dalloc(p, &p->d_state1, (size_t)p->Bp1 * G)) ||
       (rc = dalloc(p, &p->d_state2, (size_t)p->Bp2 * G)) ||
       (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems)) ||

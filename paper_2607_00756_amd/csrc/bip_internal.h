@@ -25,14 +25,15 @@ __host__ __device__ inline float2 cmulc(float2 a, float2 b) {
 __host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // ------------------------------------------------------------- plan layout
+// One atom's window as seen by the sweep gathers, in plane order.
+struct GatherRec {
+  int32_t W, oy, ox, pad;
+  int64_t off;  // element offset of the atom's [Bp][W][W] block in this side's window stack
+};
+
 struct GatherArgs {
-  const int32_t* plane_start;  // [nz + 1] atoms of plane j: plane_atoms[start[j] .. start[j+1])
-  const int32_t* plane_atoms;  // atom ids grouped by plane
-  const int32_t* W;            // [n_atoms]
-  const int32_t* oy;           // [n_atoms]
-  const int32_t* ox;           // [n_atoms]
-  const int64_t* off;          // [n_atoms] element offset of the atom's [Bp][W][W] block
-  float2* win;                 // window stack of this side
+  const GatherRec* rec;  // [n_atoms] records grouped by plane; plane j owns [begin_j, end_j)
+  float2* win;           // window stack of this side
 };
 
 // One product of the complex contraction kernel (offsets in plane elements).
@@ -137,7 +138,7 @@ struct bip_plan {
   float *d_ellw1 = nullptr, *d_ellw2 = nullptr;
   int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
   int64_t *d_off1 = nullptr, *d_off2 = nullptr;
-  int32_t *d_plane_start = nullptr, *d_plane_atoms = nullptr;
+  bip::GatherRec *d_grec1 = nullptr, *d_grec2 = nullptr;  // gather records in plane order
   float2* d_state1 = nullptr;   // [Bp1][G]
   float2* d_state2 = nullptr;   // [Bp2][G]
   float2* d_win1 = nullptr;     // window stacks

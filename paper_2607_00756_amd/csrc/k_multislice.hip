@@ -24,28 +24,29 @@ struct RowShape {
   static constexpr int LDS_ROW = NX + NX / 16; // padded complex elements per row
 };
 
+constexpr int GREC_LDS = 64;  // gather records of a plane staged in LDS
+
 // Crop the real-space row segment that falls into the windows of the atoms
-// of this plane; de-tilt by exp(-sign 2 pi i h_p.r/N) on the way.
+// of this plane; de-tilt by exp(-sign 2 pi i h_p.r/N) on the way.  Records
+// q < GREC_LDS come from LDS, the rest from memory.
 template <int NX>
 __device__ inline void gather_row(const float2 (&v)[16], int t, int y, int col, int ny,
-                                  const GatherArgs& ga, int gb, int ge, int2 hp,
-                                  const float2* __restrict__ tw, int L, int sign) {
+                                  const GatherArgs& ga, const GatherRec* srec, int gb, int ge,
+                                  int2 hp, const float2* __restrict__ tw, int L, int sign) {
   constexpr int T = RowShape<NX>::T;
-  for (int q = gb; q < ge; ++q) {
-    const int a = ga.plane_atoms[q];
-    const int W = ga.W[a];
-    int ry = y - ga.oy[a];
+  const int my = hp.x * y * (L / ny);
+  for (int q = 0; q < ge - gb; ++q) {
+    const GatherRec g = q < GREC_LDS ? srec[q] : ga.rec[gb + q];
+    int ry = y - g.oy;
     if (ry < 0) ry += ny;
-    if (ry >= W) continue;
-    float2* dst = ga.win + ga.off[a] + ((int64_t)col * W + ry) * W;
-    const int ox = ga.ox[a];
-    const int my = hp.x * y * (L / ny);
+    if (ry >= g.W) continue;
+    float2* dst = ga.win + g.off + ((int64_t)col * g.W + ry) * g.W;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int x = t + T * e;
-      int rx = x - ox;
+      int rx = x - g.ox;
       if (rx < 0) rx += NX;
-      if (rx < W) {
+      if (rx < g.W) {
         const int m = (my + hp.y * x * (L / NX)) & (L - 1);
         const float2 w = tw[m];  // exp(-2 pi i h_p.r/N)
         dst[rx] = sign > 0 ? cmul(v[e], w) : cmulc(v[e], w);
@@ -62,6 +63,12 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
                                                   GatherArgs ga, int gb, int ge, int col0) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
+  __shared__ GatherRec srec[(FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) ? GREC_LDS : 1];
+  if constexpr ((FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) != 0) {
+    // the plane's records are loaded before the state so that their latency
+    // overlaps; the FFT's barriers order them before the gather reads them
+    if ((int)threadIdx.x < ge - gb && threadIdx.x < GREC_LDS) srec[threadIdx.x] = ga.rec[gb + threadIdx.x];
+  }
   const int t = threadIdx.x % S::T;
   const int f = threadIdx.x / S::T;
   const int y = blockIdx.x * S::ROWS + f;
@@ -73,15 +80,19 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = row[t + S::T * e];
   if (FLAGS & ROW_INV) fft::transform<NX, true, 1, true>(v, my_lds, t, tw, L);
-  if ((FLAGS & ROW_GATHER_BEFORE_T) && ge > gb)
-    gather_row<NX>(v, t, y, pcol, ny, ga, gb, ge, parents[pcol], tw, L, sign);
+  if constexpr ((FLAGS & ROW_GATHER_BEFORE_T) != 0) {
+    if constexpr ((FLAGS & ROW_INV) == 0) __syncthreads();  // no transform barrier before
+    if (ge > gb) gather_row<NX>(v, t, y, pcol, ny, ga, srec, gb, ge, parents[pcol], tw, L, sign);
+  }
   if (FLAGS & ROW_T) {
     const float2* Trow = T + (int64_t)y * NX;
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = cmul(v[e], Trow[t + S::T * e]);
   }
-  if ((FLAGS & ROW_GATHER_AFTER_T) && ge > gb)
-    gather_row<NX>(v, t, y, pcol, ny, ga, gb, ge, parents[pcol], tw, L, sign);
+  if constexpr ((FLAGS & ROW_GATHER_AFTER_T) != 0) {
+    if constexpr ((FLAGS & ROW_INV) == 0) __syncthreads();
+    if (ge > gb) gather_row<NX>(v, t, y, pcol, ny, ga, srec, gb, ge, parents[pcol], tw, L, sign);
+  }
   if (FLAGS & ROW_FWD) {
     fft::transform<NX, false, 1, true>(v, my_lds, t, tw, L);
 #pragma unroll
