@@ -674,10 +674,12 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     jprobe.push_back(pj);
     det_first[i] = (int64_t)jdet.size();
     if (gram) {
-      // Gram: A = B = S2~^T [r][d] (A conjugated), output Q [r][r']
+      // Gram: A = B = S2~^T [r][d] (A conjugated, K-blocked), output Q [r][r']
       GemmJob q{};
       q.a_off = q.b_off = off[1][i];
-      q.K = q.lda = q.ldb = (int32_t)Dk;
+      q.K = (int32_t)Dk;
+      q.lda = q.ldb = gemm_bk(precision);
+      q.kstride = (int32_t)(n1_of(W) * gemm_bk(precision));
       q.m_lim = q.n_lim = W2;
       q.W2 = W2;
       q.ldo = kd;

@@ -46,7 +46,8 @@ struct GemmJob {
   int32_t ldo;           // row pitch of the output; columns >= ldo are not written
   int32_t m_lim, n_lim;  // tiles starting at or beyond these skip the job
   int32_t W2;            // window pixels of the atom
-  int32_t pad;
+  int32_t kstride;       // elements between consecutive 64-byte K chunks of a row of A and
+                         // B (0: contiguous; K-blocked operands: row count x chunk width)
 };
 
 enum Epilogue { EPI_ABS2_MAP = 0, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD };

@@ -1,8 +1,8 @@
 // Complex contractions on the matrix cores (step c).
 //
 // Every contraction is an "NT" complex product C[m][n] = sum_k A[m][k] B[n][k]
-// (optionally with conj(A)), K contiguous in both operands, each operand
-// stored as separate real planes:
+// (optionally with conj(A)), K running along the rows of both operands, each
+// operand stored as separate real planes:
 //   FP32        : re, im                          (v_mfma_f32_16x16x4_f32)
 //   SPLIT_BF16  : re_hi, re_lo, im_hi, im_lo       (v_mfma_f32_16x16x32_bf16;
 //                 hi*hi + hi*lo + lo*hi per real product, FP32 accumulate)
@@ -12,7 +12,9 @@
 //
 // Tiling: a workgroup of 4 wave64s owns a 128 x 128 output tile (each wave a
 // 64 x 64 sub-tile of 4 x 4 MFMA blocks).  K advances in 64-byte chunks per
-// plane row (16 FP32 or 32 BF16 values).  Operand chunks move from global
+// plane row (16 FP32 or 32 BF16 values); consecutive chunks of a row are
+// either adjacent (K contiguous) or a fixed stride apart (K-blocked operands,
+// where every 64-byte column block of the matrix is stored contiguously).  Operand chunks move from global
 // memory straight into LDS with global_load_lds_dwordx4 (no VGPR staging),
 // double buffered, one barrier per chunk; the 16-byte slots of each LDS row
 // are XOR-swizzled by (row / 4) mod 4 so that the 16 rows read by one MFMA
@@ -85,7 +87,7 @@ typedef __attribute__((address_space(3))) void* lptr_t;
 // l%4, which receives global segment (l%4) ^ swz(row).
 template <int PREC>
 __device__ inline void issue_chunk(const char* gbase, int64_t plane_bytes, int64_t ld_bytes,
-                                   int k0_bytes, char* lds_op, int wave, int lane) {
+                                   int64_t k0_bytes, char* lds_op, int wave, int lane) {
 #pragma unroll
   for (int p = 0; p < PT<PREC>::PLANES; ++p)
 #pragma unroll
@@ -221,9 +223,9 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
 // acc = sum over K of A[m0 + .][k] B[n0 + .][k] (A and B point at the tile origins).
 template <int PREC, bool CONJA>
 __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t lda_b, const char* B,
-                                    int64_t b_plane_b, int64_t ldb_b, int K, char* lds, int wave,
-                                    int lane, int wm, int wn, Acc& acc) {
-  constexpr int CH = 64;  // bytes per plane row per chunk
+                                    int64_t b_plane_b, int64_t ldb_b, int K, int64_t CH, char* lds,
+                                    int wave, int lane, int wm, int wn, Acc& acc) {
+  // CH: bytes between consecutive K chunks of a row (64 when K is contiguous)
   constexpr int SB = stage_bytes<PREC>();
   constexpr int OPB = PT<PREC>::PLANES * PLANE_TILE;
   const int nk = K / PT<PREC>::BK;
@@ -296,8 +298,9 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
     const char* Bp = (const char*)g.B + (job.b_off + (int64_t)n0 * job.ldb) * ESZ;
     Acc acc;
     acc.zero();
+    const int64_t ch = (job.kstride ? (int64_t)job.kstride : (int64_t)PT<PREC>::BK) * ESZ;
     tile_product<PREC, CONJA>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
-                              (int64_t)job.ldb * ESZ, job.K, smem, wave, lane, wm, wn, acc);
+                              (int64_t)job.ldb * ESZ, job.K, ch, smem, wave, lane, wm, wn, acc);
     if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)

@@ -20,7 +20,7 @@
 //   psi[u][v][r] = c sum_a exp(-2 pi i a u / S_y) X[a][v][r] is stored as the
 //   contraction operand psi^T[rho][r] (map) or as U_n = H_n psi (detector
 //   contraction), in the planes of the requested precision.
-// Both DFTs run in FP32 on the vector ALUs with twiddles rounded from FP64.
+// Both DFTs run on the FP32 matrix cores with twiddles rounded from FP64.
 #include "bip_internal.h"
 #include "planes.h"
 #include "recon_core.h"
@@ -29,33 +29,46 @@ namespace bip {
 
 namespace {
 
-constexpr int RT = 64;     // window pixels per workgroup
+constexpr int RT = 64;     // window pixels per workgroup (16 per wave)
 constexpr int NT = 256;    // threads per workgroup (4 wave64)
-constexpr int VG = 16;     // DFT outputs per thread per pass over the LDS tile
 
-// acc[k] += sum_j F[j] * T[(j * o_k) mod S] for the outputs o_k = o0 + wave + 4 k,
-// F read from the LDS column of this lane.  The twiddle index advances by o_k
-// per step (wave-uniform scalar arithmetic, no division).
-__device__ inline void dft_group(const float2* sF, const float2* sT, int S, int o0, int wave,
-                                 int lane, float2 (&acc)[VG]) {
-  int idx[VG];
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Four 16 x 16 output blocks of a DFT along the LDS rows, on the FP32 matrix
+// cores: X[o][r] = sum_{j < S} T[(o j) mod S] F[j][r] for o in
+// [obase, obase + 64) and this wave's pixels r in [16 wave, 16 wave + 16).
+// F rows S .. Sc-1 (Sc = S rounded up to 4) must be zero.  A complex block is
+// four real v_mfma_f32_16x16x4f32 products (the A operand is the twiddle,
+// lane l holding row l mod 16 and K index l / 16; the B operand is F, lane l
+// holding K index l / 16 and column l mod 16).  Output: lane l holds rows
+// obase + 16 ob + 4 (l / 16) + q, column 16 wave + l mod 16, in xr / xi[ob][q].
+__device__ inline void dft_mfma(const float2* sF, const float2* sT, int S, int obase, int wave,
+                                int lane, v4f (&xr)[4], v4f (&xi)[4]) {
+  const int li = lane & 15, lk = lane >> 4;
+  int idx[4], step[4];
 #pragma unroll
-  for (int k = 0; k < VG; ++k) {
-    acc[k] = make_float2(0.f, 0.f);
-    idx[k] = 0;
+  for (int ob = 0; ob < 4; ++ob) {
+    const int o = obase + 16 * ob + li;
+    const int oo = o < S ? o : 0;
+    idx[ob] = (oo * lk) % S;
+    step[ob] = (4 * oo) % S;
+    xr[ob] = v4f{0.f, 0.f, 0.f, 0.f};
+    xi[ob] = v4f{0.f, 0.f, 0.f, 0.f};
   }
-  for (int j = 0; j < S; ++j) {
-    const float2 F = sF[j * RT + lane];
+  const int Sc = (S + 3) & ~3;
+  for (int j0 = 0; j0 < Sc; j0 += 4) {
+    const float2 f = sF[(j0 + lk) * RT + 16 * wave + li];
 #pragma unroll
-    for (int k = 0; k < VG; ++k) {
-      const int o = o0 + wave + 4 * k;
-      if (o < S) {
-        const float2 t = sT[idx[k]];
-        acc[k].x += F.x * t.x - F.y * t.y;
-        acc[k].y += F.x * t.y + F.y * t.x;
-        idx[k] += o;
-        if (idx[k] >= S) idx[k] -= S;
+    for (int ob = 0; ob < 4; ++ob) {
+      if (obase + 16 * ob < S) {  // wave-uniform
+        const float2 e = sT[idx[ob]];
+        xr[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(e.x, f.x, xr[ob], 0, 0, 0);
+        xr[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(-e.y, f.y, xr[ob], 0, 0, 0);
+        xi[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(e.x, f.y, xi[ob], 0, 0, 0);
+        xi[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(e.y, f.x, xi[ob], 0, 0, 0);
       }
+      idx[ob] += step[ob];
+      if (idx[ob] >= S) idx[ob] -= S;
     }
   }
 }
@@ -63,8 +76,8 @@ __device__ inline void dft_group(const float2* sF, const float2* sT, int S, int 
 __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   extern __shared__ float2 sm[];
   const int Sx = pa.Sx;
-  float2* sF = sm;            // [Sx][RT]
-  float2* sT = sm + Sx * RT;  // [Sx]
+  float2* sF = sm;                         // [Sx rounded up to 4][RT]
+  float2* sT = sm + ((Sx + 3) & ~3) * RT;  // [Sx]
   const ProbeJob job = pa.jobs[blockIdx.z];
   const int W = job.W, W2 = W * W;
   const int r0 = blockIdx.x * RT;
@@ -94,16 +107,20 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
     }
     sF[c * RT + lane] = live ? F : make_float2(0.f, 0.f);
   }
+  for (int c = Sx + wave; c < ((Sx + 3) & ~3); c += 4) sF[c * RT + lane] = make_float2(0.f, 0.f);
   __syncthreads();
-  float2* X = pa.fx + job.fx_off + (int64_t)a * Sx * job.ldf + r;
-  for (int v0 = 0; v0 < Sx; v0 += 4 * VG) {
-    float2 acc[VG];
-    dft_group(sF, sT, Sx, v0, wave, lane, acc);
+  const int li = lane & 15, lk = lane >> 4;
+  float2* X = pa.fx + job.fx_off + (int64_t)a * Sx * job.ldf + r0 + 16 * wave + li;
+  for (int v0 = 0; v0 < Sx; v0 += 64) {
+    v4f xr[4], xi[4];
+    dft_mfma(sF, sT, Sx, v0, wave, lane, xr, xi);
 #pragma unroll
-    for (int k = 0; k < VG; ++k) {
-      const int v = v0 + wave + 4 * k;
-      if (v < Sx) X[(int64_t)v * job.ldf] = acc[k];
-    }
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int v = v0 + 16 * ob + 4 * lk + q;
+        if (v < Sx) X[(int64_t)v * job.ldf] = make_float2(xr[ob][q], xi[ob][q]);
+      }
   }
 }
 
@@ -111,8 +128,8 @@ template <int PREC, bool U>
 __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
   extern __shared__ float2 sm[];
   const int Sy = pa.Sy, Sx = pa.Sx;
-  float2* sG = sm;            // [Sy][RT]
-  float2* sT = sm + Sy * RT;  // [Sy]
+  float2* sG = sm;                         // [Sy rounded up to 4][RT]
+  float2* sT = sm + ((Sy + 3) & ~3) * RT;  // [Sy]
   const ProbeJob job = pa.jobs[blockIdx.z];
   const int W2 = job.W * job.W;
   const int kd = job.kd;
@@ -125,35 +142,40 @@ __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
   const int r = r0 + lane;
   const bool live = r < W2;
   const float2* X = pa.fx + job.fx_off + (int64_t)v * job.ldf + r;
-  for (int a = wave; a < Sy; a += 4)
-    sG[a * RT + lane] = live ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
+  for (int a = wave; a < ((Sy + 3) & ~3); a += 4)
+    sG[a * RT + lane] = (live && a < Sy) ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
   __syncthreads();
-  const bool in = r < kd;
+  // this lane's output pixel
+  const int li = lane & 15, lk = lane >> 4;
+  const int ro = r0 + 16 * wave + li;
+  const bool in = ro < kd, live_o = ro < W2;
   auto put = [&](int rho, float re, float im) {
     if constexpr (U) {
       for (int n = 0; n < pa.n_ch; ++n) {
-        const float2 hn = live ? pa.H[job.h_off + (int64_t)n * W2 + r] : make_float2(0.f, 0.f);
-        store_planes<PREC>(pa.out, job.out_off + ((int64_t)n * pa.Ppad + rho) * kd + r,
+        const float2 hn = live_o ? pa.H[job.h_off + (int64_t)n * W2 + ro] : make_float2(0.f, 0.f);
+        store_planes<PREC>(pa.out, job.out_off + ((int64_t)n * pa.Ppad + rho) * kd + ro,
                            pa.out_plane, hn.x * re - hn.y * im, hn.x * im + hn.y * re);
       }
     } else {
-      store_planes<PREC>(pa.out, job.out_off + (int64_t)rho * kd + r, pa.out_plane, re, im);
+      store_planes<PREC>(pa.out, job.out_off + (int64_t)rho * kd + ro, pa.out_plane, re, im);
     }
   };
-  for (int u0 = 0; u0 < Sy; u0 += 4 * VG) {
-    float2 acc[VG];
-    dft_group(sG, sT, Sy, u0, wave, lane, acc);
+  for (int u0 = 0; u0 < Sy; u0 += 64) {
+    v4f xr[4], xi[4];
+    dft_mfma(sG, sT, Sy, u0, wave, lane, xr, xi);
     if (in) {
 #pragma unroll
-      for (int k = 0; k < VG; ++k) {
-        const int u = u0 + wave + 4 * k;
-        if (u < Sy) put(u * Sx + v, pa.cb * acc[k].x, pa.cb * acc[k].y);
-      }
+      for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = u0 + 16 * ob + 4 * lk + q;
+          if (u < Sy) put(u * Sx + v, pa.cb * xr[ob][q], pa.cb * xi[ob][q]);
+        }
     }
   }
   // rows P .. Ppad-1 of the operand are zero
   if (blockIdx.y == 0 && in)
-    for (int rho = pa.P + wave; rho < pa.Ppad; rho += 4) put(rho, 0.f, 0.f);
+    for (int rho = pa.P + lk; rho < pa.Ppad; rho += 4) put(rho, 0.f, 0.f);
 }
 
 template <typename K>
@@ -167,7 +189,7 @@ hipError_t launch_lds(K kernel, dim3 grid, size_t lds, const ProbeArgs& pa, hipS
 
 }  // namespace
 
-size_t probe_lds_bytes(int S) { return (size_t)(S * RT + S) * sizeof(float2); }
+size_t probe_lds_bytes(int S) { return (size_t)(((S + 3) & ~3) * RT + S) * sizeof(float2); }
 
 hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;

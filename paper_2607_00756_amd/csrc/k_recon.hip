@@ -51,7 +51,9 @@ __global__ void k_recon_plain(ReconArgs a, float2* out) {
 }
 
 // GEMM operand output, one 64-beam x 32-pixel tile per workgroup.
-// kind 0: element (r, b) at r*ld + b  (b fastest; S2~^T for the Gram matrix)
+// kind 0: S2~^T for the Gram matrix, K-blocked: element (r, b) at
+//         ((b / KB) nrows + r) KB + b mod KB, KB = beams per 64-byte row of a
+//         plane, so each 64-byte column block is contiguous (ld unused)
 // kind 1: element (b, r) at b*ld + r  (r fastest; S2~ for the detector contraction)
 // Each half-wave computes one beam on 32 consecutive pixels, so every parent
 // read is a coalesced 256-byte row segment; the padded weight rows of the
@@ -97,26 +99,37 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
   const int py = ((a.oy + ry) & (a.ny - 1)) * (a.L / a.ny);
   const int px = ((a.ox + rx) & (a.nx - 1)) * (a.L / a.nx);
   __syncthreads();
-#pragma unroll 2
-  for (int k = 0; k < TB / 8; ++k) {
-    const int bl = 2 * wave + half + 8 * k;
-    const int b = b0 + bl;
-    float2 v = make_float2(0.f, 0.f);
-    const int2 h = s_h[bl];
-    const float2 tw = a.tw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
-    const float2 s = recon_combine(a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
-    if (b < a.nb && live) v = a.retilt_sign > 0 ? cmulc(s, tw) : cmul(s, tw);
-    tile[bl][px32] = v;
+  // four beams per batch: all their parent and carrier reads are issued
+  // before any of them is combined
+  constexpr int NBATCH = 4;
+  for (int k0 = 0; k0 < TB / 8; k0 += NBATCH) {
+    float2 D[NBATCH][ELL_K], tw[NBATCH];
+#pragma unroll
+    for (int i = 0; i < NBATCH; ++i) {
+      const int bl = 2 * wave + half + 8 * (k0 + i);
+      const int2 h = s_h[bl];
+      tw[i] = a.tw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
+      recon_load(a.win, W2, rr, s_ec[bl], D[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < NBATCH; ++i) {
+      const int bl = 2 * wave + half + 8 * (k0 + i);
+      const float2 s = recon_finish(D[i], a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
+      float2 v = make_float2(0.f, 0.f);
+      if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(s, tw[i]) : cmul(s, tw[i]);
+      tile[bl][px32] = v;
+    }
   }
   __syncthreads();
-  if (KIND == 0) {  // rows r0 + j (8 per wave), 64 consecutive beams per row
+  if (KIND == 0) {  // rows r0 + j (8 per wave), 64 consecutive beams per row, K-blocked
+    constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
 #pragma unroll 2
     for (int k = 0; k < TR / 4; ++k) {
       const int j = wave + 4 * k;
       const int ro = r0 + j, bo = b0 + lane;
       if (ro < n_r && bo < n_b) {
         const float2 v = tile[lane][j];
-        store_planes<PREC>(out, (int64_t)ro * ld + bo, plane, v.x, v.y);
+        store_planes<PREC>(out, ((int64_t)(bo / KB) * n_r + ro) * KB + bo % KB, plane, v.x, v.y);
       }
     }
   } else {  // rows b0 + j, 32 consecutive pixels per half-wave

@@ -16,15 +16,18 @@ namespace bip {
 constexpr int ELL_W = 8;  // int32 / float entries per padded row
 constexpr int ELL_K = 6;  // weights held in the padded row
 
-// z = sum_p w_p D_p(r), m = sum_p w_p |D_p(r)| (eq. window-recon); returns
-// m z/|z| in magnitude mode (eq. magpreserve, 0 where z = 0) or z.
-__device__ inline float2 recon_combine(const float2* __restrict__ win, int W2, int rr,
-                                       const int32_t* ec, const float* ew,
-                                       const int32_t* __restrict__ col,
-                                       const float* __restrict__ w, int mode) {
-  float2 D[ELL_K];
+// The six padded parent values of one target beam at pixel rr.
+__device__ inline void recon_load(const float2* __restrict__ win, int W2, int rr, const int32_t* ec,
+                                  float2 (&D)[ELL_K]) {
 #pragma unroll
   for (int j = 0; j < ELL_K; ++j) D[j] = win[(int64_t)ec[j] * W2 + rr];
+}
+
+// Combination of loaded parent values (see recon_combine).
+__device__ inline float2 recon_finish(const float2 (&D)[ELL_K], const float2* __restrict__ win,
+                                      int W2, int rr, const int32_t* ec, const float* ew,
+                                      const int32_t* __restrict__ col,
+                                      const float* __restrict__ w, int mode) {
   float2 z = make_float2(0.f, 0.f);
   float m = 0.f;
 #pragma unroll
@@ -47,6 +50,17 @@ __device__ inline float2 recon_combine(const float2* __restrict__ win, int W2, i
     return az > 0.f ? cscale(z, m / az) : make_float2(0.f, 0.f);
   }
   return z;
+}
+
+// z = sum_p w_p D_p(r), m = sum_p w_p |D_p(r)| (eq. window-recon); returns
+// m z/|z| in magnitude mode (eq. magpreserve, 0 where z = 0) or z.
+__device__ inline float2 recon_combine(const float2* __restrict__ win, int W2, int rr,
+                                       const int32_t* ec, const float* ew,
+                                       const int32_t* __restrict__ col,
+                                       const float* __restrict__ w, int mode) {
+  float2 D[ELL_K];
+  recon_load(win, W2, rr, ec, D);
+  return recon_finish(D, win, W2, rr, ec, ew, col, w, mode);
 }
 
 }  // namespace bip
