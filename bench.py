@@ -124,6 +124,24 @@ def cpu_baseline(sp):
     }
 
 
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None
+    when there is none for this stage or the kernel's sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("stage") != stage:
+        return None
+    for src, sha in t.get("sources_sha256", {}).items():
+        p = os.path.join(ROOT, src)
+        if not os.path.exists(p) or hashlib.sha256(open(p, "rb").read()).hexdigest() != sha:
+            return None
+    return float(t["bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -212,6 +230,7 @@ def main():
     launches_per_step = dom_n / args.steps
     amount, unit, bound, peak = work[dom]
     achieved = amount / launches_per_step / (dom_ms / dom_n / 1e3)
+    traffic = measured_traffic(dom)
     per_stage = {k: {"rate": (w[0] / (stages[k][0] / args.steps / 1e3) if stages[k][0] > 0 else None),
                      "unit": w[1], "bound": w[2], "frac": (w[0] / (stages[k][0] / args.steps / 1e3) / w[3]
                                                             if stages[k][0] > 0 else None)}
@@ -240,7 +259,8 @@ def main():
                    "column_batch": int(plan.query(bip.Q_SCALARS)[2])},
         "roofline": {"bound": bound, "kernel": names[dom], "stage": dom,
                      "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                     "traffic": None, "launches_per_step": launches_per_step,
+                     "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
+                     "launches_per_step": launches_per_step,
                      "avg_launch_ms": dom_ms / dom_n},
         "stage_rooflines": per_stage,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
