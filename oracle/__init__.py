@@ -15,4 +15,7 @@ Modules
   eels       -- Alg. 1 (conventional), Alg. 4 (exact dual matrix),
                 Alg. 5 (BiP-PRISM), windowed reconstruction, contraction,
                 output reductions, on-atom diagnostic
+  adjoint    -- gradient of a map loss through Alg. 5 (slice potentials,
+                transition potentials, atom positions)
+  potential  -- slice potentials from atom positions and their gradient
 """
