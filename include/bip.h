@@ -64,6 +64,9 @@ typedef struct bip_optics {
   double theta_rad;     /* collection semi-angle: detector |q| <= theta/lambda        */
   int32_t partition;    /* parent lattice factor s >= 1 (s = 1: exact PRISM)         */
   int32_t recon_mode;   /* BIP_RECON_MAGNITUDE (eq. magpreserve) or BIP_RECON_COMPLEX */
+  int32_t ckpt_stride;  /* 0: forward only; 1: bip_build_smatrix also keeps the
+                           transmitted state of every parent column at every slice
+                           (slice checkpoints) so that bip_eels_backward can run */
 } bip_optics;
 
 typedef struct bip_plan bip_plan;
@@ -150,6 +153,60 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
                     const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
                     int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
                     void* stream);
+
+/*
+ * bip_eels_backward -- gradient of a map loss (step a16: adjoint of steps
+ * a5..a14).  Passage: the forward model's multislice (eq. smatrix-advance,
+ * eq. s2), eq. window-recon / eq. magpreserve and eq. coupling / eq. map-sum,
+ * differentiated by hand in reverse order.
+ * Requires a plan created with ckpt_stride = 1 and a bip_build_smatrix of the
+ * same V: the reverse sweeps read the slice checkpoints it kept.  All atoms
+ * of the plan contribute; the map is the one bip_eels_signal returns for
+ * out_mode BIP_OUT_MAP with the same H and raster.  The contraction is
+ * recomputed in FP32 whatever precision the forward map used.
+ *   H, H_off, n_ch, scan_sy/sx   as for bip_eels_signal.
+ *   dL_dI      device f32 [P]: dL/dI(rho) of the loss L(I) (e.g. 2 (I - I_t)).
+ *   dL_dV      device f32 [nz][ny][nx], overwritten: dL/dV_j(r).
+ *   dL_dHconj  device complex64, ragged like H, or NULL: the Wirtinger
+ *              derivative dL/d conj(H_n(r)) (dL = 2 Re sum conj(g) dH).
+ *   dHdx, dHdy device complex64, ragged like H, or NULL: dH/dtau_x, dH/dtau_y
+ *              of each atom's transition potentials on its window.
+ *   dL_dtau_xy host f64 [n_atoms][2] or NULL (needs dHdx, dHdy): the position
+ *              gradient through the transition potentials, 2 Re sum conj(g) dH/dtau;
+ *              when given, the call synchronizes the stream.
+ * The position gradient through the slice potentials is bip_potential_grad
+ * of dL_dV.  Deterministic: no atomics, fixed reduction orders.
+ * Errors: BIP_EINVAL, BIP_ESTATE (no build, or no checkpoints),
+ * BIP_EUNSUPPORTED (raster sides above 256), BIP_ENOMEM, BIP_EHIP.
+ */
+int bip_eels_backward(bip_plan* plan, int32_t n_ch, const float* H, const int64_t* H_off,
+                      int32_t scan_sy, int32_t scan_sx, const float* dL_dI, float* dL_dV,
+                      float* dL_dHconj, const float* dHdx, const float* dHdy, double* dL_dtau_xy,
+                      void* stream);
+
+/*
+ * bip_potential_build -- slice potentials from atom positions (the forward
+ * model's projected potential, read as a Gaussian sum): atom a adds
+ * sum_k amp[a][k] exp(-|r - r_a|^2 / (2 width[k]^2)) to slice floor(z_a/dz)
+ * (clamped), periodic images out to 10 width[k]; evaluated in FP64.
+ *   xyz    host f64 [n_atoms][3] (x, y, z) in A.
+ *   amp    host f64 [n_atoms][n_terms] in V*A; width host f64 [n_terms] in A.
+ *   V      device f32 [nz][ny][nx], overwritten.
+ * Allocates temporary device memory and synchronizes the stream.
+ */
+int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                        const double* amp, const double* width, float* V, void* stream);
+
+/*
+ * bip_potential_grad -- dL/dxyz of every atom from dL/dV (the adjoint of
+ * bip_potential_build): dL/dx_a = sum_r dL/dV_j(r) dv_a(r)/dx_a, likewise y;
+ * dL/dz = 0 (slice membership is piecewise constant).
+ *   dL_dV    device f32 [nz][ny][nx];  dL_dxyz  host f64 [n_atoms][3], overwritten.
+ * Allocates temporary device memory and synchronizes the stream.
+ */
+int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                       const double* amp, const double* width, const float* dL_dV,
+                       double* dL_dxyz, void* stream);
 
 /*
  * bip_parent_windows -- the cropped, de-tilted parent windows gathered by

@@ -12,7 +12,7 @@ import os
 import numpy as np
 # torch first: its bundled HIP runtime (SONAME libamdhip64.so.7) must be the one
 # libbip.so binds to, so that the process holds a single HIP/HSA runtime.
-import torch  # noqa: F401
+import torch
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libbip.so")
 if not os.path.exists(_LIB_PATH):
@@ -28,6 +28,7 @@ Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_W
 
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
+           "bip_eels_backward", "bip_potential_build", "bip_potential_grad",
            "bip_plan_destroy", "bip_last_error"]
 STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "probe_fold",
           "probe_dft", "det_gemm", "reduce", "gram_gemm"]
@@ -41,7 +42,7 @@ class BipGrid(ctypes.Structure):
 class BipOptics(ctypes.Structure):
     _fields_ = [("energy_ev", ctypes.c_double), ("alpha_rad", ctypes.c_double),
                 ("theta_rad", ctypes.c_double), ("partition", ctypes.c_int32),
-                ("recon_mode", ctypes.c_int32)]
+                ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32)]
 
 
 _p = ctypes.c_void_p
@@ -55,10 +56,16 @@ _lib.bip_parent_windows.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p]
 _lib.bip_query.argtypes = [_p, ctypes.c_int32, _p]
 _lib.bip_set_profiling.argtypes = [_p, ctypes.c_int32]
 _lib.bip_stage_timings.argtypes = [_p, _p, _p, ctypes.c_int32]
+_lib.bip_eels_backward.argtypes = [_p, ctypes.c_int32, _p, _p, ctypes.c_int32, ctypes.c_int32, _p,
+                                   _p, _p, _p, _p, _p, _p]
+_lib.bip_potential_build.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
+                                     _p, _p, _p, _p]
+_lib.bip_potential_grad.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
+                                    _p, _p, _p, _p, _p]
 _lib.bip_plan_destroy.argtypes = [_p]
 _lib.bip_plan_destroy.restype = None
 _lib.bip_last_error.restype = ctypes.c_char_p
-for _f in EXPORTS[:8]:
+for _f in EXPORTS[:11]:
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -92,10 +99,11 @@ class Plan:
     """A bip_plan: geometry, parents, Sibson weights and device workspace."""
 
     def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
-                 win_size, win_origin, recon_mode=RECON_MAGNITUDE, stream=None):
+                 win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None):
         self._h = _p()
         grid = BipGrid(ny, nx, nz, ly, lx, dz)
-        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode)
+        self.grid = grid
+        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride)
         tau, tp = _host(tau_xyz, np.float64)
         ws, wp = _host(win_size, np.int32)
         wo, op = _host(win_origin, np.int32)
@@ -149,6 +157,21 @@ class Plan:
                                     int(scan[1]), int(out_mode), int(precision), _ptr(out),
                                     _stream(stream)))
 
+    def eels_backward(self, n_ch, H, H_off, scan, dL_dI, dL_dV, dL_dHconj=None, dHdx=None,
+                      dHdy=None, want_tau=False, stream=None):
+        """Gradient of a map loss (plan made with ckpt_stride=1, after build_smatrix).
+        dL_dI: float32 device [P]; dL_dV: float32 device [nz, ny, nx] (written);
+        dL_dHconj / dHdx / dHdy: complex64 device, ragged like H, or None.
+        Returns dL/dtau_xy [n_atoms, 2] (float64) when want_tau, else None."""
+        offs, op = _host(H_off, np.int64)
+        tau = np.zeros((self.n_atoms, 2), np.float64) if want_tau else None
+        _check(_lib.bip_eels_backward(self._h, int(n_ch), _ptr(H), op, int(scan[0]), int(scan[1]),
+                                      _ptr(dL_dI), _ptr(dL_dV), _ptr(dL_dHconj), _ptr(dHdx),
+                                      _ptr(dHdy),
+                                      tau.ctypes.data_as(ctypes.c_void_p) if want_tau else None,
+                                      _stream(stream)))
+        return tau
+
     def set_profiling(self, enable):
         _check(_lib.bip_set_profiling(self._h, 1 if enable else 0))
 
@@ -184,6 +207,73 @@ class Plan:
             raise ValueError(what)
         _check(_lib.bip_query(self._h, what, buf.ctypes.data_as(ctypes.c_void_p)))
         return buf
+
+
+def potential_build(grid, xyz, amp, width, V, stream=None):
+    """Slice potentials V (float32 device [nz, ny, nx]) from atom positions
+    xyz [n, 3], amplitudes amp [n, K] and widths [K] (host arrays)."""
+    x, xp = _host(xyz, np.float64)
+    a, ap = _host(amp, np.float64)
+    w, wp = _host(width, np.float64)
+    _check(_lib.bip_potential_build(ctypes.byref(grid), int(x.shape[0]), xp, int(w.size), ap, wp,
+                                    _ptr(V), _stream(stream)))
+
+
+def potential_grad(grid, xyz, amp, width, dL_dV, stream=None):
+    """dL/dxyz [n, 3] (float64, host) from dL/dV (float32 device)."""
+    x, xp = _host(xyz, np.float64)
+    a, ap = _host(amp, np.float64)
+    w, wp = _host(width, np.float64)
+    out = np.zeros((x.shape[0], 3), np.float64)
+    _check(_lib.bip_potential_grad(ctypes.byref(grid), int(x.shape[0]), xp, int(w.size), ap, wp,
+                                   _ptr(dL_dV), out.ctypes.data_as(ctypes.c_void_p),
+                                   _stream(stream)))
+    return out
+
+
+class EELSMap(torch.autograd.Function):
+    """I = map(V, H) through bip_build_smatrix + bip_eels_signal; backward
+    through bip_eels_backward.  The plan must be made with ckpt_stride=1.
+    Gradients follow torch's complex convention (2 dL/d conj(H) for H)."""
+
+    @staticmethod
+    def forward(ctx, V, H, plan, n_ch, H_off, scan, precision):
+        P = int(scan[0]) * int(scan[1])
+        out = torch.empty(P, dtype=torch.float32, device=V.device)
+        plan.build_smatrix(V.contiguous())
+        plan.eels_signal(n_ch, H.contiguous(), H_off, scan, OUT_MAP, precision, out)
+        ctx.plan, ctx.n_ch, ctx.H_off, ctx.scan = plan, n_ch, H_off, scan
+        ctx.save_for_backward(V, H)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_I):
+        V, H = ctx.saved_tensors
+        dV = torch.empty_like(V)
+        gH = torch.empty_like(H) if ctx.needs_input_grad[1] else None
+        # the checkpoints belong to the last build: rebuild if another V was built since
+        ctx.plan.build_smatrix(V.contiguous())
+        ctx.plan.eels_backward(ctx.n_ch, H.contiguous(), ctx.H_off, ctx.scan,
+                               grad_I.contiguous().float(), dV, dL_dHconj=gH)
+        return dV, (2.0 * gH if gH is not None else None), None, None, None, None, None
+
+
+class SlicePotential(torch.autograd.Function):
+    """V = potential(xyz) through bip_potential_build; backward through
+    bip_potential_grad (host float64 positions, returned as a CPU tensor)."""
+
+    @staticmethod
+    def forward(ctx, xyz, grid, amp, width, shape):
+        V = torch.empty(shape, dtype=torch.float32, device="cuda")
+        x = xyz.detach().cpu().numpy()
+        potential_build(grid, x, amp, width, V)
+        ctx.grid, ctx.x, ctx.amp, ctx.width = grid, x, amp, width
+        return V
+
+    @staticmethod
+    def backward(ctx, grad_V):
+        g = potential_grad(ctx.grid, ctx.x, ctx.amp, ctx.width, grad_V.contiguous().float())
+        return torch.from_numpy(g), None, None, None, None
 
 
 def library_path() -> str:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "bip_internal.h"
+#include "host_common.h"
 #include "recon_core.h"
 
 namespace bip {
@@ -41,43 +42,6 @@ double interaction(double ev) {
 }
 
 bool pow2_in_range(int n) { return n >= 64 && n <= 1024 && (n & (n - 1)) == 0; }
-int64_t roundup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-
-int err(int code, const std::string& msg) {
-  set_error(msg);
-  return code;
-}
-
-#define HIPCHK(expr, what)                         \
-  do {                                             \
-    hipError_t e_ = (expr);                        \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
-
-hipEvent_t take_event(bip_plan* p) {
-  if (!p->event_pool.empty()) {
-    hipEvent_t e = p->event_pool.back();
-    p->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Run `launch` on stream `st`; when profiling, bracket it with events.
-template <typename F>
-hipError_t timed(bip_plan* p, int stage, hipStream_t st, F&& launch) {
-  if (!p->profiling) return launch();
-  hipEvent_t a = take_event(p), b = take_event(p);
-  if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, st);
-  if (e == hipSuccess) e = launch();
-  if (e == hipSuccess) e = hipEventRecord(b, st);
-  p->timed.push_back({stage, a, b});
-  return e;
-}
-
 // Fold recorded event pairs into the per-stage totals (synchronizes them).
 int collect_timings(bip_plan* p) {
   for (auto& t : p->timed) {
@@ -91,29 +55,6 @@ int collect_timings(bip_plan* p) {
     p->event_pool.push_back(t.b);
   }
   p->timed.clear();
-  return BIP_OK;
-}
-
-template <typename T>
-int dalloc(bip_plan* p, T** out, size_t count) {
-  *out = nullptr;
-  if (count == 0) return BIP_OK;
-  void* ptr = nullptr;
-  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return err(BIP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  p->allocations.push_back(ptr);
-  *out = (T*)ptr;
-  return BIP_OK;
-}
-
-template <typename T>
-int upload(bip_plan* p, T** out, const std::vector<T>& v, hipStream_t s) {
-  int rc = dalloc(p, out, v.size());
-  if (rc) return rc;
-  if (!v.empty()) HIPCHK(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
   return BIP_OK;
 }
 
@@ -189,73 +130,6 @@ int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector
   return BIP_OK;
 }
 
-struct Workspace {
-  char* base = nullptr;
-  size_t used = 0;
-  void* take(size_t bytes) {
-    void* p = base + used;
-    used += roundup((int64_t)bytes, 256);
-    return p;
-  }
-};
-
-int ensure_work(bip_plan* p, size_t bytes) {
-  if (p->work_bytes >= bytes) return BIP_OK;
-  if (p->d_work) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p->d_work);
-    p->d_work = nullptr;
-    p->work_bytes = 0;
-  }
-  hipError_t e = hipMalloc(&p->d_work, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    p->d_work = nullptr;
-    return err(BIP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes");
-  }
-  p->work_bytes = bytes;
-  return BIP_OK;
-}
-
-// Parent columns per sweep batch: BIP_COLUMN_BATCH if set (0 = all columns),
-// else as many as fit in kColumnBatchBytes of state.
-constexpr int64_t kColumnBatchBytes = (int64_t)192 << 20;
-int column_batch(int64_t G) {
-  const char* env = std::getenv("BIP_COLUMN_BATCH");
-  int64_t b = env ? std::atoll(env) : kColumnBatchBytes / (G * 8);
-  if (b <= 0) b = INT32_MAX;
-  return (int)std::min<int64_t>(b, INT32_MAX);
-}
-
-GatherArgs gather_args(const bip_plan* p, int side) {
-  GatherArgs g;
-  g.rec = side == 1 ? p->d_grec1 : p->d_grec2;
-  g.win = side == 1 ? p->d_win1 : p->d_win2;
-  return g;
-}
-
-ReconArgs recon_args(const bip_plan* p, int a, int side) {
-  ReconArgs r;
-  r.win = (side == 1 ? p->d_win1 + p->off1[a] : p->d_win2 + p->off2[a]);
-  r.rowptr = side == 1 ? p->d_rp1 : p->d_rp2;
-  r.col = side == 1 ? p->d_col1 : p->d_col2;
-  r.w = side == 1 ? p->d_w1 : p->d_w2;
-  r.ellc = side == 1 ? p->d_ellc1 : p->d_ellc2;
-  r.ellw = side == 1 ? p->d_ellw1 : p->d_ellw2;
-  r.beams = side == 1 ? p->d_beams : p->d_det;
-  r.nb = side == 1 ? p->B : p->ndet;
-  r.W = p->W[a];
-  r.oy = p->oy[a];
-  r.ox = p->ox[a];
-  r.ny = p->g.ny;
-  r.nx = p->g.nx;
-  r.tw = p->d_tw;
-  r.L = p->L;
-  r.retilt_sign = side == 1 ? +1 : -1;
-  r.mode = p->o.recon_mode;
-  return r;
-}
-
 }  // namespace
 }  // namespace bip
 
@@ -296,6 +170,9 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   if (o.partition < 1) return err(BIP_EINVAL, "partition must be >= 1");
   if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
     return err(BIP_EINVAL, "unknown recon_mode");
+  if (o.ckpt_stride < 0) return err(BIP_EINVAL, "ckpt_stride must be >= 0");
+  if (o.ckpt_stride > 1)
+    return err(BIP_EUNSUPPORTED, "ckpt_stride above 1 (recomputed segments) is not implemented");
   if (n_atoms < 1) return err(BIP_EINVAL, "n_atoms must be >= 1");
   for (int a = 0; a < n_atoms; ++a) {
     const int W = win_size[a];
@@ -417,9 +294,18 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems)) ||
       (rc = dalloc(p, &p->d_win2, (size_t)p->win2_elems)))
     return fail(rc);
+  if (o.ckpt_stride == 1) {
+    const size_t n1 = (size_t)p->i_max * p->Bp1 * G, n2 = (size_t)(g.nz - p->i_min) * p->Bp2 * G;
+    if ((rc = dalloc(p, &p->d_prop_conj, G)) || (n1 && (rc = dalloc(p, &p->d_ckpt1, n1))) ||
+        (rc = dalloc(p, &p->d_ckpt2, n2)) || (rc = dalloc(p, &p->d_gwin1, (size_t)p->win1_elems)) ||
+        (rc = dalloc(p, &p->d_gwin2, (size_t)p->win2_elems)))
+      return fail(rc);
+  }
   hipError_t e = launch_twiddles(p->d_tw, p->L, st);
   if (e == hipSuccess)
-    e = launch_prop_table(p->d_prop, g.ny, g.nx, g.ly, g.lx, p->lambda, g.dz, st);
+    e = launch_prop_table(p->d_prop, g.ny, g.nx, g.ly, g.lx, p->lambda, g.dz, 0, st);
+  if (e == hipSuccess && p->d_prop_conj)
+    e = launch_prop_table(p->d_prop_conj, g.ny, g.nx, g.ly, g.lx, p->lambda, g.dz, 1, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(hip_fail(e, "plan tables"));
   *out = p;
@@ -448,8 +334,13 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
       int flags = ROW_GATHER_BEFORE_T;
       if (j > 0) flags |= ROW_INV;
       if (j < p->i_max) flags |= ROW_T | ROW_FWD;
+      float2* save = nullptr;
+      if (p->d_ckpt1 && j < p->i_max) {
+        flags |= ROW_SAVE;
+        save = p->d_ckpt1 + ((int64_t)j * p->Bp1 + c0) * G;
+      }
       HIPCHK(timed(p, ST_S1_ROW, st, [&] { return launch_row_pass(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                             p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], c0, st); }),
+                             p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], c0, save, st); }),
              "S1 row pass");
       if (j < p->i_max)
         HIPCHK(timed(p, ST_S1_COL, st, [&] { return launch_col_pass(s1, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
@@ -465,15 +356,20 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
     const int nc = std::min(batch, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
     HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, s2, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
-                           p->d_par2, -1, g2, 0, 0, c0, st); }),
+                           p->d_par2, -1, g2, 0, 0, c0, nullptr, st); }),
            "S2 row transform");
     for (int j = g.nz - 1; j >= p->i_min; --j) {
       HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
              "S2 column pass");
       int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
       if (j > p->i_min) flags |= ROW_FWD;
+      float2* save = nullptr;
+      if (p->d_ckpt2) {
+        flags |= ROW_SAVE;
+        save = p->d_ckpt2 + ((int64_t)(j - p->i_min) * p->Bp2 + c0) * G;
+      }
       HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                             p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, st); }),
+                             p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, save, st); }),
              "S2 row pass");
     }
   }

@@ -1,0 +1,504 @@
+// C ABI of the map-loss gradient: bip_eels_backward, and the slice-potential
+// helpers bip_potential_build / bip_potential_grad.
+//
+// The backward recomputes, atom by atom, what the forward contraction used
+// (psi, S2~, the Gram matrix) in FP32, forms the cotangents of the parent
+// windows, then runs the two parent sweeps in reverse with the slice
+// checkpoints kept by bip_build_smatrix (ckpt_stride = 1), injecting the
+// window cotangents at their planes and reducing dL/dV in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "bip_internal.h"
+#include "host_common.h"
+
+namespace bip {
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kAdjGroups = 64;  // column groups of the adjoint row pass
+
+// parent -> (beam, weight) lists of a CSR beam -> parent weight matrix
+void transpose_csr(const std::vector<int32_t>& rp, const std::vector<int32_t>& col,
+                   const std::vector<double>& w, int n_par, std::vector<int32_t>& trp,
+                   std::vector<int32_t>& tb, std::vector<float>& tw) {
+  const int nb = (int)rp.size() - 1;
+  trp.assign(n_par + 1, 0);
+  for (int32_t c : col) trp[c + 1]++;
+  for (int p = 0; p < n_par; ++p) trp[p + 1] += trp[p];
+  std::vector<int32_t> fill(trp.begin(), trp.end() - 1);
+  tb.assign(col.size(), 0);
+  tw.assign(col.size(), 0.f);
+  for (int b = 0; b < nb; ++b)
+    for (int k = rp[b]; k < rp[b + 1]; ++k) {
+      const int q = fill[col[k]]++;
+      tb[q] = b;
+      tw[q] = (float)w[k];
+    }
+}
+
+}  // namespace
+}  // namespace bip
+
+using namespace bip;
+
+extern "C" {
+
+int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
+                      int32_t scan_sy, int32_t scan_sx, const float* dL_dI, float* dL_dV,
+                      float* dL_dHconj, const float* dHdx, const float* dHdy, double* dL_dtau_xy,
+                      void* stream) {
+  if (!p || !H || !H_off || !dL_dI || !dL_dV) return err(BIP_EINVAL, "NULL argument");
+  if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
+  if (!p->d_ckpt2) return err(BIP_ESTATE, "plan created without slice checkpoints (ckpt_stride 0)");
+  if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
+  if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
+  if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)
+    return err(BIP_EUNSUPPORTED, "scan raster sides above " + std::to_string(BIP_MAX_SCAN));
+  if ((dHdx == nullptr) != (dHdy == nullptr)) return err(BIP_EINVAL, "dHdx and dHdy go together");
+  if (dL_dtau_xy && !dHdx) return err(BIP_EINVAL, "dL_dtau_xy needs dHdx and dHdy");
+  for (int a = 0; a < p->n_atoms; ++a)
+    if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
+      return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
+  hipStream_t st = (hipStream_t)stream;
+  const bip_grid& g = p->g;
+  const int64_t G = (int64_t)g.ny * g.nx;
+  const int P = scan_sy * scan_sx;
+  const int64_t Ppad = roundup(P, 128);
+  const int64_t Dpad = roundup(p->ndet, 128), Dk = roundup(p->ndet, 32);
+  const int BKF = gemm_bk(BIP_PREC_FP32);
+  int Wmax = 0;
+  for (int a = 0; a < p->n_atoms; ++a) Wmax = std::max(Wmax, p->W[a]);
+  const int64_t W2m = (int64_t)Wmax * Wmax, kdm = roundup(W2m, 32), n1m = roundup(W2m, 128),
+                ldfm = roundup(W2m, 64);
+  // host tables: residue cells, synthesis and adjoint twiddles, probe jobs
+  std::vector<int32_t>& cells = p->h_cells;
+  cells.assign((size_t)P + 1 + p->B, 0);
+  {
+    std::vector<int32_t> cell_of(p->B);
+    for (int b = 0; b < p->B; ++b) {
+      const int hy = p->beams[2 * b], hx = p->beams[2 * b + 1];
+      cell_of[b] = (((hy % scan_sy) + scan_sy) % scan_sy) * scan_sx + ((hx % scan_sx) + scan_sx) % scan_sx;
+      cells[cell_of[b] + 1]++;
+    }
+    for (int i = 0; i < P; ++i) cells[i + 1] += cells[i];
+    std::vector<int32_t> fill(cells.begin(), cells.begin() + P);
+    for (int b = 0; b < p->B; ++b) cells[P + 1 + fill[cell_of[b]]++] = b;
+  }
+  std::vector<float2>& tws = p->h_tws;  // twx, twy, conj(twx), conj(twy)
+  tws.resize(2 * ((size_t)scan_sx + scan_sy));
+  for (int k = 0; k < scan_sx; ++k) {
+    const double t = 2.0 * kPi * k / scan_sx;
+    tws[k] = make_float2((float)std::cos(t), (float)-std::sin(t));
+    tws[scan_sx + scan_sy + k] = make_float2((float)std::cos(t), (float)std::sin(t));
+  }
+  for (int k = 0; k < scan_sy; ++k) {
+    const double t = 2.0 * kPi * k / scan_sy;
+    tws[scan_sx + k] = make_float2((float)std::cos(t), (float)-std::sin(t));
+    tws[2 * scan_sx + scan_sy + k] = make_float2((float)std::cos(t), (float)std::sin(t));
+  }
+  std::vector<ProbeJob>& jprobe = p->h_probe;
+  jprobe.assign(p->n_atoms, ProbeJob{});
+  for (int a = 0; a < p->n_atoms; ++a) {
+    ProbeJob& j = jprobe[a];
+    j.win_off = p->off1[a];
+    j.h_off = H_off[a];
+    j.W = p->W[a];
+    j.oy = p->oy[a];
+    j.ox = p->ox[a];
+    j.kd = (int32_t)roundup((int64_t)p->W[a] * p->W[a], 32);
+    j.ldf = (int32_t)roundup((int64_t)p->W[a] * p->W[a], 64);
+  }
+  // transposed weights (parent -> beams), built once per plan
+  if (!p->d_tp1_rp) {
+    std::vector<int32_t> rp, tb;
+    std::vector<float> tw;
+    int rc;
+    transpose_csr(p->rp1, p->col1, p->w1, p->Bp1, rp, tb, tw);
+    if ((rc = upload(p, &p->d_tp1_rp, rp, st)) || (rc = upload(p, &p->d_tp1_b, tb, st)) ||
+        (rc = upload(p, &p->d_tp1_w, tw, st)))
+      return rc;
+    transpose_csr(p->rp2, p->col2, p->w2, p->Bp2, rp, tb, tw);
+    if ((rc = upload(p, &p->d_tp2_rp, rp, st)) || (rc = upload(p, &p->d_tp2_b, tb, st)) ||
+        (rc = upload(p, &p->d_tp2_w, tw, st)))
+      return rc;
+    HIPCHK(hipStreamSynchronize(st), "weight tables");  // the host vectors go out of scope
+  }
+  // workspace (one atom at a time, sized for the largest window)
+  const int nbmax = std::max(p->B, p->ndet);
+  const int batch = p->column_batch > 0 ? p->column_batch : std::max(p->Bp1, p->Bp2);
+  const int groups = std::min(kAdjGroups, std::max(1, batch));
+  size_t need = 0;
+  auto sz = [&](size_t bytes) { need += (size_t)roundup((int64_t)bytes, 256); };
+  sz((size_t)P * ldfm * 8);        // X / Y
+  sz((size_t)P * ldfm * 8);        // Z
+  sz((size_t)2 * Ppad * kdm * 4);  // psi^T planes
+  sz((size_t)2 * n1m * Dk * 4);    // S2~ K-blocked planes
+  sz((size_t)2 * Dpad * kdm * 4);  // S2~ [d][r] planes
+  sz((size_t)2 * n1m * kdm * 4);   // Q planes
+  sz((size_t)n1m * kdm * 8);       // G
+  sz((size_t)2 * n1m * Ppad * 4);  // A1
+  sz((size_t)2 * n1m * Ppad * 4);  // B1
+  sz((size_t)n1m * kdm * 8);       // R
+  sz((size_t)2 * n1m * kdm * 4);   // K planes
+  sz((size_t)Ppad * kdm * 8);      // g_psi
+  sz((size_t)Dpad * kdm * 8);      // g_S2~
+  sz((size_t)nbmax * W2m * 8);     // g_z
+  sz((size_t)nbmax * W2m * 4);     // gamma
+  sz((size_t)n_ch * W2m * 8);      // g_H scratch
+  sz((size_t)Ppad * 4);            // Ibar
+  sz((size_t)p->n_atoms * 16);     // dtau
+  sz((size_t)groups * G * 4);      // dV partials
+  sz(cells.size() * 4);
+  sz(tws.size() * 8);
+  sz(jprobe.size() * sizeof(ProbeJob));
+  sz(3 * (size_t)p->n_atoms * sizeof(GemmJob));
+  int rc = ensure_work(p, need + 4096);
+  if (rc) return rc;
+  Workspace ws{(char*)p->d_work, 0};
+  float2* X = (float2*)ws.take((size_t)P * ldfm * 8);
+  float2* Z = (float2*)ws.take((size_t)P * ldfm * 8);
+  float* psiT = (float*)ws.take((size_t)2 * Ppad * kdm * 4);
+  float* S2b = (float*)ws.take((size_t)2 * n1m * Dk * 4);
+  float* S2d = (float*)ws.take((size_t)2 * Dpad * kdm * 4);
+  float* Qp = (float*)ws.take((size_t)2 * n1m * kdm * 4);
+  float2* Gm = (float2*)ws.take((size_t)n1m * kdm * 8);
+  float* A1 = (float*)ws.take((size_t)2 * n1m * Ppad * 4);
+  float* B1 = (float*)ws.take((size_t)2 * n1m * Ppad * 4);
+  float2* R = (float2*)ws.take((size_t)n1m * kdm * 8);
+  float* Kp = (float*)ws.take((size_t)2 * n1m * kdm * 4);
+  float2* gpsi = (float2*)ws.take((size_t)Ppad * kdm * 8);
+  float2* gS2 = (float2*)ws.take((size_t)Dpad * kdm * 8);
+  float2* gz = (float2*)ws.take((size_t)nbmax * W2m * 8);
+  float* gam = (float*)ws.take((size_t)nbmax * W2m * 4);
+  float2* gHs = (float2*)ws.take((size_t)n_ch * W2m * 8);
+  float* ibar = (float*)ws.take((size_t)Ppad * 4);
+  double* dtau = (double*)ws.take((size_t)p->n_atoms * 16);
+  float* dvp = (float*)ws.take((size_t)groups * G * 4);
+  int32_t* d_cells = (int32_t*)ws.take(cells.size() * 4);
+  float2* d_tws = (float2*)ws.take(tws.size() * 8);
+  ProbeJob* d_probe = (ProbeJob*)ws.take(jprobe.size() * sizeof(ProbeJob));
+  GemmJob* d_jobs = (GemmJob*)ws.take(3 * (size_t)p->n_atoms * sizeof(GemmJob));
+  if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: backward workspace");
+  HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
+  HIPCHK(hipMemcpyAsync(d_tws, tws.data(), tws.size() * 8, hipMemcpyHostToDevice, st), "twiddles");
+  HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
+  HIPCHK(launch_zero(ibar, Ppad, st), "zero");
+  HIPCHK(hipMemcpyAsync(ibar, dL_dI, (size_t)P * 4, hipMemcpyDeviceToDevice, st), "dL/dI");
+  HIPCHK(launch_zero((float*)p->d_gwin1, 2 * p->win1_elems, st), "zero");
+  HIPCHK(launch_zero((float*)p->d_gwin2, 2 * p->win2_elems, st), "zero");
+  const float cb = (float)(1.0 / std::sqrt((double)g.ny * g.nx * p->B));
+  ProbeArgs pa{};
+  pa.win = p->d_win1;
+  pa.rowptr = p->d_rp1;
+  pa.col = p->d_col1;
+  pa.w = p->d_w1;
+  pa.ellc = p->d_ellc1;
+  pa.ellw = p->d_ellw1;
+  pa.beams = p->d_beams;
+  pa.cell_start = d_cells;
+  pa.cell_beams = d_cells + P + 1;
+  pa.twx = d_tws;
+  pa.twy = d_tws + scan_sx;
+  pa.tw = p->d_tw;
+  pa.L = p->L;
+  pa.ny = g.ny;
+  pa.nx = g.nx;
+  pa.mode = p->o.recon_mode;
+  pa.Sy = scan_sy;
+  pa.Sx = scan_sx;
+  pa.P = P;
+  pa.Ppad = (int)Ppad;
+  pa.cb = cb;
+  pa.fx = X;
+  pa.out = psiT;
+  pa.out_plane = Ppad * kdm;
+  pa.H = (const float2*)H;
+  pa.n_ch = n_ch;
+  const float2* twxc = d_tws + scan_sx + scan_sy;
+  const float2* twyc = twxc + scan_sx;
+  // ---------------------------------------------------------- per atom
+  // three products per atom: Gram (G, Q), R, and the two gradient products
+  std::vector<GemmJob>& hj = p->h_jobs2;
+  hj.assign(3 * (size_t)p->n_atoms, GemmJob{});
+  for (int a = 0; a < p->n_atoms; ++a) {
+    const int W2 = p->W[a] * p->W[a];
+    const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
+    GemmJob& q = hj[3 * a];
+    q.K = (int32_t)Dk;
+    q.lda = q.ldb = BKF;
+    q.kstride = (int32_t)(n1 * BKF);
+    q.m_lim = q.n_lim = W2;
+    q.W2 = W2;
+    q.ldo = (int32_t)kd;
+    q.h_off = H_off[a];
+    GemmJob& rj = hj[3 * a + 1];
+    rj.K = rj.lda = rj.ldb = (int32_t)Ppad;
+    rj.m_lim = rj.n_lim = W2;
+    rj.W2 = W2;
+    rj.ldo = (int32_t)kd;
+    GemmJob& uj = hj[3 * a + 2];
+    uj.K = uj.lda = uj.ldb = (int32_t)kd;
+    uj.m_lim = (int32_t)std::max(Ppad, Dpad);
+    uj.n_lim = W2;
+    uj.W2 = W2;
+    uj.ldo = (int32_t)kd;
+  }
+  HIPCHK(hipMemcpyAsync(d_jobs, hj.data(), hj.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
+  for (int a = 0; a < p->n_atoms; ++a) {
+    const int W = p->W[a], W2 = W * W;
+    const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128), ldf = roundup(W2, 64);
+    const float2* Ha = (const float2*)H + H_off[a];
+    GemmJob* jobs_a = d_jobs + 3 * a;
+    // psi^T [rho][r] (FP32), exactly as the forward synthesis
+    pa.jobs = d_probe + a;
+    HIPCHK(launch_probe_fold_x(pa, W2, 1, st), "probe fold");
+    HIPCHK(launch_probe_y(pa, BIP_PREC_FP32, false, (int)kd, 1, st), "probe synthesis");
+    // S2~ K-blocked (Gram) and [d][r] (gradient product), FP32
+    HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2b, 0, BIP_PREC_FP32, Dk, n1, Dk, n1 * Dk, st), "recon S2");
+    HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2d, 1, BIP_PREC_FP32, kd, Dpad, kd, Dpad * kd, st), "recon S2");
+    // Gram matrix G and Q = G o Hc
+    GemmArgs ga{};
+    ga.H = (const float2*)H;
+    ga.n_ch = n_ch;
+    ga.A = ga.B = S2b;
+    ga.a_plane = ga.b_plane = n1 * Dk;
+    ga.jobs = jobs_a;
+    ga.njobs = 1;
+    ga.out = Qp;
+    ga.out_plane = n1 * kd;
+    ga.out2 = Gm;
+    ga.tiles = (int)(n1 / 128);
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_GRAMQ, ga, (int)gemm_gram_blocks(ga.tiles, 1), 1, 1, st), "Gram");
+    // R = conj(psi) diag(Ibar) psi^T over the raster
+    HIPCHK(launch_psi_transpose(psiT, Ppad * kdm, (int)kd, W2, P, (int)Ppad, (int)n1, ibar, A1, B1,
+                                n1 * Ppad, st), "psi transpose");
+    GemmArgs gr{};
+    gr.A = A1;
+    gr.B = B1;
+    gr.a_plane = gr.b_plane = n1 * Ppad;
+    gr.jobs = jobs_a + 1;
+    gr.njobs = 1;
+    gr.out = R;
+    gr.m_store = (int)n1;
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE + EPI_CONJ_A, gr, (int)(n1 / 128), (int)(n1 / 128), 1, st), "R");
+    HIPCHK(launch_kmat(R, Ha, n_ch, W2, (int)kd, (int)n1, Kp, n1 * kd, st), "K");
+    // g_psi = Ibar (Q psi) and g_S2~ = S2~ K^T
+    GemmArgs gp{};
+    gp.A = psiT;
+    gp.a_plane = Ppad * kdm;
+    gp.B = Qp;
+    gp.b_plane = n1 * kd;
+    gp.jobs = jobs_a + 2;
+    gp.njobs = 1;
+    gp.out = gpsi;
+    gp.rowscale = ibar;
+    gp.m_store = (int)Ppad;
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gp, (int)(Ppad / 128), (int)(n1 / 128), 1, st), "g_psi");
+    GemmArgs gs{};
+    gs.A = S2d;
+    gs.a_plane = Dpad * kd;
+    gs.B = Kp;
+    gs.b_plane = n1 * kd;
+    gs.jobs = jobs_a + 2;
+    gs.njobs = 1;
+    gs.out = gS2;
+    gs.m_store = (int)Dpad;
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gs, (int)(Dpad / 128), (int)(n1 / 128), 1, st), "g_S2");
+    // transition-potential cotangent and the position gradient through H
+    float2* gH = dL_dHconj ? (float2*)dL_dHconj + H_off[a] : gHs;
+    HIPCHK(launch_grad_h(Gm, R, Ha, n_ch, W2, (int)kd, gH, st), "g_H");
+    if (dHdx)
+      HIPCHK(launch_grad_tau(gH, (const float2*)dHdx + H_off[a], (const float2*)dHdy + H_off[a],
+                             n_ch * W2, dtau + 2 * a, st), "dtau");
+    // adjoint of the probe sum: Z[a][c][r] = sum_{u,v} exp(+2 pi i (a u/S_y + c v/S_x)) g_psi
+    HIPCHK(launch_dft_pass(gpsi, X, scan_sx, kd, scan_sx * kd, ldf, scan_sx * ldf, scan_sy, W2, twxc, st), "adjoint DFT x");
+    HIPCHK(launch_dft_pass(X, Z, scan_sy, scan_sx * ldf, ldf, scan_sx * ldf, ldf, scan_sx, W2, twyc, st), "adjoint DFT y");
+    // reconstruction adjoints -> window cotangents
+    HIPCHK(launch_recon_adjoint(recon_args(p, a, 1), 1, Z, ldf, scan_sy, scan_sx, cb, gz, gam,
+                                p->d_par1, p->Bp1, p->d_tp1_rp, p->d_tp1_b, p->d_tp1_w,
+                                p->d_gwin1 + p->off1[a], st), "recon adjoint S1");
+    HIPCHK(launch_recon_adjoint(recon_args(p, a, 2), 2, gS2, kd, scan_sy, scan_sx, cb, gz, gam,
+                                p->d_par2, p->Bp2, p->d_tp2_rp, p->d_tp2_b, p->d_tp2_w,
+                                p->d_gwin2 + p->off2[a], st), "recon adjoint S2");
+  }
+  // ----------------------------------------------------- reverse sweeps
+  HIPCHK(launch_zero(dL_dV, G * g.nz, st), "zero dV");
+  const float two_sigma = (float)(2.0 * p->sigma);
+  GatherArgs inj1{p->d_grec1, p->d_gwin1}, inj2{p->d_grec2, p->d_gwin2};
+  auto ps = [&](int j) { return p->plane_start[j]; };
+  // S1: psi_{j+1} = P(T_j psi_j); windows of plane j come from psi_j
+  if (p->i_max > 0) {
+    for (int c0 = 0; c0 < p->Bp1; c0 += batch) {
+      const int nc = std::min(batch, p->Bp1 - c0);
+      float2* s1 = p->d_state1 + (int64_t)c0 * G;
+      const int grp = std::min(groups, nc);
+      const int i = p->i_max;
+      HIPCHK(launch_row_adjoint(ADJ_ZERO | ADJ_INJ_AFTER | ADJ_FWD, s1, nc, g.ny, g.nx, nullptr,
+                                p->d_tw, p->L, inj1, ps(i), ps(i + 1), c0, nullptr, 0.f, nullptr, grp, st),
+             "S1 adjoint start");
+      for (int j = p->i_max - 1; j >= 0; --j) {
+        HIPCHK(launch_col_pass(s1, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S1 adjoint column pass");
+        int flags = ADJ_INV | ADJ_DV;
+        if (j > 0) flags |= ADJ_CONJT | ADJ_INJ_AFTER | ADJ_FWD;
+        HIPCHK(launch_row_adjoint(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj1,
+                                  ps(j), ps(j + 1), c0, p->d_ckpt1 + ((int64_t)j * p->Bp1 + c0) * G,
+                                  two_sigma, dvp, grp, st),
+               "S1 adjoint row pass");
+        HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+      }
+    }
+  }
+  // S2: v_j = T_j P v_{j+1}; windows of plane j come from v_j
+  for (int c0 = 0; c0 < p->Bp2; c0 += batch) {
+    const int nc = std::min(batch, p->Bp2 - c0);
+    float2* s2 = p->d_state2 + (int64_t)c0 * G;
+    const int grp = std::min(groups, nc);
+    for (int j = p->i_min; j < g.nz; ++j) {
+      int flags = ADJ_INJ_BEFORE | ADJ_DV;
+      flags |= j == p->i_min ? ADJ_ZERO : ADJ_INV;
+      if (j < g.nz - 1) flags |= ADJ_CONJT | ADJ_FWD;
+      if (j > p->i_min)
+        HIPCHK(launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S2 adjoint column pass");
+      HIPCHK(launch_row_adjoint(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj2, ps(j),
+                                ps(j + 1), c0, p->d_ckpt2 + ((int64_t)(j - p->i_min) * p->Bp2 + c0) * G,
+                                two_sigma, dvp, grp, st),
+             "S2 adjoint row pass");
+      HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+    }
+  }
+  if (dL_dtau_xy) {
+    HIPCHK(hipMemcpyAsync(dL_dtau_xy, dtau, (size_t)p->n_atoms * 16, hipMemcpyDeviceToHost, st), "dtau");
+    HIPCHK(hipStreamSynchronize(st), "dtau");
+  }
+  return BIP_OK;
+}
+
+int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                        const double* amp, const double* width, float* V, void* stream);
+int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                       const double* amp, const double* width, const float* dL_dV,
+                       double* dL_dxyz, void* stream);
+
+}  // extern "C"
+
+namespace {
+
+// Terms (x, y, A, w) of every (atom, Gaussian) grouped by slice.
+int slice_terms(const bip_grid& g, int n_atoms, const double* xyz, int n_terms, const double* amp,
+                const double* width, std::vector<double>& terms, std::vector<int64_t>& start,
+                std::vector<int32_t>& owner) {
+  if (g.nz < 1 || g.ny < 1 || g.nx < 1 || !(g.ly > 0) || !(g.lx > 0) || !(g.dz > 0))
+    return err(BIP_EINVAL, "bad grid");
+  if (n_atoms < 0 || n_terms < 1) return err(BIP_EINVAL, "n_atoms >= 0 and n_terms >= 1");
+  for (int k = 0; k < n_terms; ++k)
+    if (!(width[k] > 0)) return err(BIP_EINVAL, "widths must be > 0");
+  std::vector<std::vector<int32_t>> by(g.nz);
+  for (int a = 0; a < n_atoms; ++a) {
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(xyz[3 * a + c])) return err(BIP_EINVAL, "non-finite atom position");
+    const int j = std::min(std::max((int)std::floor(xyz[3 * a + 2] / g.dz), 0), g.nz - 1);
+    by[j].push_back(a);
+  }
+  terms.clear();
+  owner.clear();
+  start.assign(g.nz + 1, 0);
+  for (int j = 0; j < g.nz; ++j) {
+    for (int a : by[j])
+      for (int k = 0; k < n_terms; ++k) {
+        terms.insert(terms.end(), {xyz[3 * a], xyz[3 * a + 1], amp[(int64_t)a * n_terms + k], width[k]});
+        owner.push_back(a);
+      }
+    start[j + 1] = (int64_t)owner.size();
+  }
+  return BIP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                        const double* amp, const double* width, float* V, void* stream) {
+  if (!grid || !V || (n_atoms > 0 && (!xyz || !amp)) || !width) return err(BIP_EINVAL, "NULL argument");
+  const bip_grid g = *grid;
+  std::vector<double> terms;
+  std::vector<int64_t> start;
+  std::vector<int32_t> owner;
+  int rc = slice_terms(g, n_atoms, xyz, n_terms, amp, width, terms, start, owner);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t most = 1;
+  for (int j = 0; j < g.nz; ++j) most = std::max(most, start[j + 1] - start[j]);
+  double *d_terms = nullptr, *d_prof = nullptr;
+  hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)most * (g.ny + g.nx) * 8);
+  if (e == hipSuccess && !terms.empty())
+    e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
+  for (int j = 0; j < g.nz && e == hipSuccess; ++j) {
+    const int nt = (int)(start[j + 1] - start[j]);
+    const double* tj = d_terms + 4 * start[j];
+    float* Vj = V + (int64_t)j * g.ny * g.nx;
+    e = launch_profiles(tj, nt, g.ny, g.nx, g.ly, g.lx, 0, d_prof, nullptr, st);
+    if (e == hipSuccess) e = launch_build_slice(tj, d_prof, nt, g.ny, g.nx, Vj, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_terms);
+  (void)hipFree(d_prof);
+  if (e != hipSuccess) return hip_fail(e, "potential build");
+  return BIP_OK;
+}
+
+int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
+                       const double* amp, const double* width, const float* dL_dV,
+                       double* dL_dxyz, void* stream) {
+  if (!grid || !dL_dV || !dL_dxyz || (n_atoms > 0 && (!xyz || !amp)) || !width)
+    return err(BIP_EINVAL, "NULL argument");
+  const bip_grid g = *grid;
+  std::vector<double> terms;
+  std::vector<int64_t> start;
+  std::vector<int32_t> owner;
+  int rc = slice_terms(g, n_atoms, xyz, n_terms, amp, width, terms, start, owner);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  int64_t most = 1;
+  for (int j = 0; j < g.nz; ++j) most = std::max(most, start[j + 1] - start[j]);
+  const size_t nt_all = owner.size();
+  double *d_terms = nullptr, *d_prof = nullptr, *d_dprof = nullptr, *d_out = nullptr;
+  hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)most * (g.ny + g.nx) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_dprof, (size_t)most * (g.ny + g.nx) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_out, std::max<size_t>(nt_all, 1) * 16);
+  if (e == hipSuccess && !terms.empty())
+    e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
+  for (int j = 0; j < g.nz && e == hipSuccess; ++j) {
+    const int nt = (int)(start[j + 1] - start[j]);
+    if (nt == 0) continue;
+    const double* tj = d_terms + 4 * start[j];
+    e = launch_profiles(tj, nt, g.ny, g.nx, g.ly, g.lx, 1, d_prof, d_dprof, st);
+    if (e == hipSuccess)
+      e = launch_grad_terms(tj, d_prof, d_dprof, nt, g.ny, g.nx, dL_dV + (int64_t)j * g.ny * g.nx,
+                            d_out + 2 * start[j], st);
+  }
+  std::vector<double> out(2 * nt_all);
+  if (e == hipSuccess && nt_all)
+    e = hipMemcpyAsync(out.data(), d_out, out.size() * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_terms);
+  (void)hipFree(d_prof);
+  (void)hipFree(d_dprof);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "potential gradient");
+  for (int a = 0; a < n_atoms; ++a) dL_dxyz[3 * a] = dL_dxyz[3 * a + 1] = dL_dxyz[3 * a + 2] = 0.0;
+  for (size_t t = 0; t < nt_all; ++t) {  // terms in slice order, atoms' terms in order
+    dL_dxyz[3 * owner[t]] += out[2 * t];
+    dL_dxyz[3 * owner[t] + 1] += out[2 * t + 1];
+  }
+  return BIP_OK;
+}
+
+}  // extern "C"

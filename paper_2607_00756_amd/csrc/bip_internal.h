@@ -50,7 +50,7 @@ struct GemmJob {
                          // B (0: contiguous; K-blocked operands: row count x chunk width)
 };
 
-enum Epilogue { EPI_ABS2_MAP = 0, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD };
+enum Epilogue { EPI_ABS2_MAP = 0, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD, EPI_STORE };
 
 struct GemmArgs {
   const void* A;
@@ -68,6 +68,9 @@ struct GemmArgs {
   int ndet, P;
   int tiles;                 // EPI_GRAMQ: 128-row tiles per side (upper triangle launched)
   int zsplit;                // EPI_QUAD: job groups along grid z, one partial row each
+  float2* out2;              // EPI_GRAMQ: also store G itself (complex64 [r][r'], pitch ldo)
+  const float* rowscale;     // EPI_STORE: optional real factor per output row
+  int m_store;               // EPI_STORE: rows >= m_store are not written
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {
@@ -144,6 +147,14 @@ struct bip_plan {
   float2* d_state2 = nullptr;   // [Bp2][G]
   float2* d_win1 = nullptr;     // window stacks
   float2* d_win2 = nullptr;
+  // gradient state (ckpt_stride = 1)
+  float2* d_prop_conj = nullptr;  // conj(P(q)) / G
+  float2* d_ckpt1 = nullptr;      // [i_max][Bp1][G]: S1 after T_j, slices 0 .. i_max-1
+  float2* d_ckpt2 = nullptr;      // [nz - i_min][Bp2][G]: S2 after T_j, slices i_min .. nz-1
+  float2* d_gwin1 = nullptr;      // window cotangents, laid out like the window stacks
+  float2* d_gwin2 = nullptr;
+  int32_t *d_tp1_rp = nullptr, *d_tp1_b = nullptr, *d_tp2_rp = nullptr, *d_tp2_b = nullptr;
+  float *d_tp1_w = nullptr, *d_tp2_w = nullptr;  // parent -> beam weights (backward)
   int64_t win1_elems = 0, win2_elems = 0;
   // signal workspace (grown on demand)
   void* d_work = nullptr;
@@ -177,8 +188,9 @@ int hip_fail(hipError_t e, const char* what);
 // ----------------------------------------------------------- launchers
 // setup (k_setup.hip)
 hipError_t launch_twiddles(float2* tw, int L, hipStream_t s);
+// P(q)/G, or its conjugate (the inverse propagation of the adjoint sweeps)
 hipError_t launch_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
-                             double dz, hipStream_t s);
+                             double dz, int conj, hipStream_t s);
 hipError_t launch_transmit(float2* T, const float* V, int64_t n, float sigma, hipStream_t s);
 hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, int nx,
                                   const float2* tw, int L, int sign, float scale, hipStream_t s);
@@ -186,12 +198,26 @@ hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p,
                          hipStream_t st);
 
 // multislice (k_multislice.hip)
-enum RowFlags { ROW_INV = 1, ROW_T = 2, ROW_FWD = 4, ROW_GATHER_BEFORE_T = 8, ROW_GATHER_AFTER_T = 16 };
-// state points at the first column of the batch; col0 is that column's parent index
+enum RowFlags {
+  ROW_INV = 1, ROW_T = 2, ROW_FWD = 4, ROW_GATHER_BEFORE_T = 8, ROW_GATHER_AFTER_T = 16,
+  ROW_SAVE = 32  // write the state after T_j to `save` (slice checkpoint, [ncols][ny][nx])
+};
+// state (and save) point at the first column of the batch; col0 is that column's parent index
 hipError_t launch_row_pass(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
                            const float2* tw, int L, const int2* parents, int detilt_sign,
                            const GatherArgs& ga, int gather_begin, int gather_end, int col0,
-                           hipStream_t s);
+                           float2* save, hipStream_t s);
+// adjoint sweeps (the cotangent state replaces the forward state)
+enum AdjFlags {
+  ADJ_ZERO = 1, ADJ_INV = 2, ADJ_INJ_BEFORE = 4, ADJ_DV = 8, ADJ_CONJT = 16, ADJ_INJ_AFTER = 32,
+  ADJ_FWD = 64
+};
+// grid: (ny / rows-per-block, groups); dv_partial [groups][ny][nx]; ckpt at the batch's first column
+hipError_t launch_row_adjoint(int flags, float2* state, int ncols, int ny, int nx, const float2* T,
+                              const float2* tw, int L, const GatherArgs& inj, int gb, int ge,
+                              int col0, const float2* ckpt, float two_sigma, float* dv_partial,
+                              int groups, hipStream_t s);
+hipError_t launch_dv_reduce(const float* partial, int n_groups, int64_t n, float* dv, hipStream_t s);
 hipError_t launch_col_pass(float2* state, int ncols, int ny, int nx, const float2* prop,
                            const float2* tw, int L, hipStream_t s);
 
@@ -227,9 +253,40 @@ hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipS
 hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int n_jobs,
                           hipStream_t s);
 
+// strided DFT pass of the probe-sum adjoint (k_probe.hip)
+hipError_t launch_dft_pass(const float2* in, float2* out, int S, int64_t js, int64_t os, int64_t ks,
+                           int64_t os2, int n_outer, int W2, const float2* tws, hipStream_t s);
+
+// gradient kernels (k_backward.hip)
+hipError_t launch_psi_transpose(const float* psiT, int64_t psp, int kd, int W2, int P, int Ppad,
+                                int n1, const float* ibar, float* A1, float* B1, int64_t apl,
+                                hipStream_t s);
+hipError_t launch_kmat(const float2* R, const float2* H, int n_ch, int W2, int kd, int n1, float* Kp,
+                       int64_t kpl, hipStream_t s);
+hipError_t launch_grad_h(const float2* G, const float2* R, const float2* H, int n_ch, int W2, int kd,
+                         float2* gH, hipStream_t s);
+hipError_t launch_grad_tau(const float2* gH, const float2* dHx, const float2* dHy, int n,
+                           double* out, hipStream_t s);
+hipError_t launch_recon_adjoint(const ReconArgs& a, int side, const float2* gsrc, int64_t ld_src,
+                                int Sy, int Sx, float cb, float2* gz, float* gam,
+                                const int2* parents, int Bp, const int32_t* tp_rp,
+                                const int32_t* tp_b, const float* tp_w, float2* gwin,
+                                hipStream_t s);
+
+// slice potentials (k_potential.hip); terms are (x, y, A, w) quadruples of one slice
+hipError_t launch_profiles(const double* terms, int n_terms, int ny, int nx, double ly, double lx,
+                           int deriv, double* prof, double* dprof, hipStream_t s);
+hipError_t launch_build_slice(const double* terms, const double* prof, int n_terms, int ny, int nx,
+                              float* V, hipStream_t s);
+hipError_t launch_grad_terms(const double* terms, const double* prof, const double* dprof,
+                             int n_terms, int ny, int nx, const float* dV, double* out,
+                             hipStream_t s);
+
 // contraction (k_gemm.hip)
-// grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit); for
-// EPI_GRAMQ a 1-D grid of gemm_gram_blocks(g.tiles, njobs) workgroups
+// grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit), (m_tiles,
+// n_tiles, njobs) for EPI_STORE; for EPI_GRAMQ a 1-D grid of gemm_gram_blocks(g.tiles,
+// njobs) workgroups.  epi EPI_STORE + EPI_CONJ_A conjugates the A operand.
+constexpr int EPI_CONJ_A = 16;
 hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s);
 int64_t gemm_gram_blocks(int tiles, int njobs);

@@ -1,0 +1,142 @@
+// Host-side helpers shared by the C-ABI entry points (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "bip_internal.h"
+
+namespace bip {
+
+inline int64_t roundup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+inline int err(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+#define HIPCHK(expr, what)                         \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+inline hipEvent_t take_event(bip_plan* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` on stream `st`; when profiling, bracket it with events.
+template <typename F>
+hipError_t timed(bip_plan* p, int stage, hipStream_t st, F&& launch) {
+  if (!p->profiling) return launch();
+  hipEvent_t a = take_event(p), b = take_event(p);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, st);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  p->timed.push_back({stage, a, b});
+  return e;
+}
+
+template <typename T>
+int dalloc(bip_plan* p, T** out, size_t count) {
+  *out = nullptr;
+  if (count == 0) return BIP_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return err(BIP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  p->allocations.push_back(ptr);
+  *out = (T*)ptr;
+  return BIP_OK;
+}
+
+template <typename T>
+int upload(bip_plan* p, T** out, const std::vector<T>& v, hipStream_t s) {
+  int rc = dalloc(p, out, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  return BIP_OK;
+}
+
+struct Workspace {
+  char* base = nullptr;
+  size_t used = 0;
+  void* take(size_t bytes) {
+    void* p = base + used;
+    used += roundup((int64_t)bytes, 256);
+    return p;
+  }
+};
+
+inline int ensure_work(bip_plan* p, size_t bytes) {
+  if (p->work_bytes >= bytes) return BIP_OK;
+  if (p->d_work) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_work);
+    p->d_work = nullptr;
+    p->work_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&p->d_work, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_work = nullptr;
+    return err(BIP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes");
+  }
+  p->work_bytes = bytes;
+  return BIP_OK;
+}
+
+// Parent columns per sweep batch: BIP_COLUMN_BATCH if set (0 = all columns),
+// else as many as fit in kColumnBatchBytes of state.
+constexpr int64_t kColumnBatchBytes = (int64_t)192 << 20;
+inline int column_batch(int64_t G) {
+  const char* env = std::getenv("BIP_COLUMN_BATCH");
+  int64_t b = env ? std::atoll(env) : kColumnBatchBytes / (G * 8);
+  if (b <= 0) b = INT32_MAX;
+  return (int)std::min<int64_t>(b, INT32_MAX);
+}
+
+inline GatherArgs gather_args(const bip_plan* p, int side) {
+  GatherArgs g;
+  g.rec = side == 1 ? p->d_grec1 : p->d_grec2;
+  g.win = side == 1 ? p->d_win1 : p->d_win2;
+  return g;
+}
+
+inline ReconArgs recon_args(const bip_plan* p, int a, int side) {
+  ReconArgs r;
+  r.win = (side == 1 ? p->d_win1 + p->off1[a] : p->d_win2 + p->off2[a]);
+  r.rowptr = side == 1 ? p->d_rp1 : p->d_rp2;
+  r.col = side == 1 ? p->d_col1 : p->d_col2;
+  r.w = side == 1 ? p->d_w1 : p->d_w2;
+  r.ellc = side == 1 ? p->d_ellc1 : p->d_ellc2;
+  r.ellw = side == 1 ? p->d_ellw1 : p->d_ellw2;
+  r.beams = side == 1 ? p->d_beams : p->d_det;
+  r.nb = side == 1 ? p->B : p->ndet;
+  r.W = p->W[a];
+  r.oy = p->oy[a];
+  r.ox = p->ox[a];
+  r.ny = p->g.ny;
+  r.nx = p->g.nx;
+  r.tw = p->d_tw;
+  r.L = p->L;
+  r.retilt_sign = side == 1 ? +1 : -1;
+  r.mode = p->o.recon_mode;
+  return r;
+}
+
+}  // namespace bip

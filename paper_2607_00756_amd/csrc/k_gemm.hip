@@ -30,6 +30,8 @@
 //              sum_n conj(H_n(r)) H_n(r') -> Q (operand of EPI_QUAD)
 //   EPI_QUAD   (Q psi)(r, rho); I(rho) += Re sum_r conj(psi(r, rho)) (Q psi)(r, rho)
 //              accumulated over atoms, then summed over the tile's r
+//   EPI_STORE  the product itself as complex64 (optionally scaled per row):
+//              the contractions of the map-loss gradient
 // For the map, sum_n sum_d |a_d|^2 = psi^H Q psi exactly, which replaces the
 // n_det x N_ch P detector contraction by a W^2 x W^2 Gram matrix per atom.
 #include "bip_internal.h"
@@ -279,6 +281,9 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
     if constexpr (EPI == EPI_QUAD) {  // job group z of g.zsplit
       jb0 = (int)((int64_t)g.njobs * blockIdx.z / g.zsplit);
       jb1 = (int)((int64_t)g.njobs * (blockIdx.z + 1) / g.zsplit);
+    } else if constexpr (EPI == EPI_STORE) {  // one job per grid z
+      jb0 = (int)blockIdx.z;
+      jb1 = jb0 + 1;
     } else {
       jb0 = 0;
       jb1 = g.njobs;
@@ -323,6 +328,23 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
             sq[bm][bn][v] += ps.x * acc.re[bm][bn][v] + ps.y * acc.im[bm][bn][v];
           }
       }
+    } else if constexpr (EPI == EPI_STORE) {
+      float2* o = (float2*)g.out;
+#pragma unroll
+      for (int bn = 0; bn < 4; ++bn) {
+        const int n = n0 + wn * 64 + bn * 16 + lr;
+        if (n >= job.ldo) continue;
+#pragma unroll
+        for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int m = m0 + wm * 64 + bm * 16 + kg * 4 + v;
+            if (m >= g.m_store) continue;
+            const float s = g.rowscale ? g.rowscale[m] : 1.f;
+            o[job.out_off + (int64_t)m * job.ldo + n] =
+                make_float2(s * acc.re[bm][bn][v], s * acc.im[bm][bn][v]);
+          }
+      }
     } else {
       // EPI_GRAMQ: element (m, n) = (r, r') of Q = G * sum_c conj(H_c(r)) H_c(r')
 #pragma unroll
@@ -352,6 +374,12 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
             if (m0 != n0 && m < job.ldo)
               store_planes<PREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
                                  -qi);
+            if (g.out2) {  // G itself, for the gradient
+              const bool in = m < job.W2 && n < job.W2;
+              g.out2[job.out_off + (int64_t)m * job.ldo + n] = in ? make_float2(cr, ci) : make_float2(0.f, 0.f);
+              if (m0 != n0 && m < job.ldo)
+                g.out2[job.out_off + (int64_t)n * job.ldo + m] = in ? make_float2(cr, -ci) : make_float2(0.f, 0.f);
+            }
           }
       }
     }
@@ -451,6 +479,8 @@ hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
     case EPI_ABS2_BEAMS: return zgemm_launch<PREC, EPI_ABS2_BEAMS, false>(g, grid, s);
     case EPI_GRAMQ: return zgemm_launch<PREC, EPI_GRAMQ, true>(g, grid, s);
     case EPI_QUAD: return zgemm_launch<PREC, EPI_QUAD, false>(g, grid, s);
+    case EPI_STORE: return zgemm_launch<PREC, EPI_STORE, false>(g, grid, s);
+    case EPI_STORE + EPI_CONJ_A: return zgemm_launch<PREC, EPI_STORE, true>(g, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -178,6 +178,42 @@ __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
     for (int rho = pa.P + lk; rho < pa.Ppad; rho += 4) put(rho, 0.f, 0.f);
 }
 
+// One strided DFT pass of the probe-sum adjoint: for every outer index o and
+// window pixel r < W2,
+//   out[k ks + o os2 + r] = sum_j T[(j k) mod S] in[j js + o os + r],
+// with T = exp(+2 pi i k/S) (the conjugate of the synthesis twiddles).
+__global__ __launch_bounds__(NT) void k_dft_pass(const float2* __restrict__ in, float2* out, int S,
+                                                 int64_t js, int64_t os, int64_t ks, int64_t os2,
+                                                 int W2, const float2* __restrict__ tws) {
+  extern __shared__ float2 sm[];
+  float2* sF = sm;
+  float2* sT = sm + ((S + 3) & ~3) * RT;
+  const int o = blockIdx.y;
+  const int r0 = blockIdx.x * RT;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int i = threadIdx.x; i < S; i += NT) sT[i] = tws[i];
+  const int r = r0 + lane;
+  for (int j = wave; j < ((S + 3) & ~3); j += 4)
+    sF[j * RT + lane] = (r < W2 && j < S) ? in[(int64_t)j * js + (int64_t)o * os + r] : make_float2(0.f, 0.f);
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  const int ro = r0 + 16 * wave + li;
+  for (int k0 = 0; k0 < S; k0 += 64) {
+    v4f xr[4], xi[4];
+    dft_mfma(sF, sT, S, k0, wave, lane, xr, xi);
+    if (ro < W2) {
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + 16 * ob + 4 * lk + q;
+          if (k < S) out[(int64_t)k * ks + (int64_t)o * os2 + ro] = make_float2(xr[ob][q], xi[ob][q]);
+        }
+    }
+  }
+}
+
 template <typename K>
 hipError_t launch_lds(K kernel, dim3 grid, size_t lds, const ProbeArgs& pa, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)kernel,
@@ -190,6 +226,18 @@ hipError_t launch_lds(K kernel, dim3 grid, size_t lds, const ProbeArgs& pa, hipS
 }  // namespace
 
 size_t probe_lds_bytes(int S) { return (size_t)(((S + 3) & ~3) * RT + S) * sizeof(float2); }
+
+hipError_t launch_dft_pass(const float2* in, float2* out, int S, int64_t js, int64_t os, int64_t ks,
+                          int64_t os2, int n_outer, int W2, const float2* tws, hipStream_t s) {
+  if (n_outer <= 0 || W2 <= 0) return hipSuccess;
+  const size_t lds = probe_lds_bytes(S);
+  hipError_t e = hipFuncSetAttribute((const void*)k_dft_pass,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dft_pass, dim3((W2 + RT - 1) / RT, n_outer), dim3(NT), lds, s, in, out, S,
+                     js, os, ks, os2, W2, tws);
+  return hipGetLastError();
+}
 
 hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;

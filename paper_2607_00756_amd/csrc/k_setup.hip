@@ -23,7 +23,7 @@ hipError_t launch_twiddles(float2* tw, int L, hipStream_t s) {
 // normalized.  The phase reaches tens of radians on large grids, so it is
 // formed and reduced in FP64.
 __global__ void k_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
-                             double dz) {
+                             double dz, int conj) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   int y = blockIdx.y;
   if (x >= nx) return;
@@ -36,13 +36,13 @@ __global__ void k_prop_table(float2* prop, int ny, int nx, double ly, double lx,
   double s, c;
   sincospi(t, &s, &c);
   double g = 1.0 / ((double)ny * (double)nx);
-  prop[(size_t)y * nx + x] = make_float2((float)(c * g), (float)(s * g));
+  prop[(size_t)y * nx + x] = make_float2((float)(c * g), (float)((conj ? -s : s) * g));
 }
 
 hipError_t launch_prop_table(float2* prop, int ny, int nx, double ly, double lx, double lambda,
-                             double dz, hipStream_t s) {
+                             double dz, int conj, hipStream_t s) {
   hipLaunchKernelGGL(k_prop_table, dim3((nx + 255) / 256, ny), dim3(256), 0, s, prop, ny, nx, ly,
-                     lx, lambda, dz);
+                     lx, lambda, dz, conj);
   return hipGetLastError();
 }
 

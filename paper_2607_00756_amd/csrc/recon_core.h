@@ -52,6 +52,31 @@ __device__ inline float2 recon_finish(const float2 (&D)[ELL_K], const float2* __
   return z;
 }
 
+// z and m of one target beam from loaded parent values (the intermediates of
+// the reconstruction that its adjoint needs).
+__device__ inline void recon_zm(const float2 (&D)[ELL_K], const float2* __restrict__ win, int W2,
+                                int rr, const int32_t* ec, const float* ew,
+                                const int32_t* __restrict__ col, const float* __restrict__ w,
+                                float2& z, float& m) {
+  z = make_float2(0.f, 0.f);
+  m = 0.f;
+#pragma unroll
+  for (int j = 0; j < ELL_K; ++j) {
+    const float wj = ew[j];
+    z.x += wj * D[j].x;
+    z.y += wj * D[j].y;
+    m += wj * sqrtf(D[j].x * D[j].x + D[j].y * D[j].y);
+  }
+  const int cnt = ec[6], lo = ec[7];
+  for (int j = lo + ELL_K; j < lo + cnt; ++j) {
+    const float2 Dj = win[(int64_t)col[j] * W2 + rr];
+    const float wj = w[j];
+    z.x += wj * Dj.x;
+    z.y += wj * Dj.y;
+    m += wj * sqrtf(Dj.x * Dj.x + Dj.y * Dj.y);
+  }
+}
+
 // z = sum_p w_p D_p(r), m = sum_p w_p |D_p(r)| (eq. window-recon); returns
 // m z/|z| in magnitude mode (eq. magpreserve, 0 where z = 0) or z.
 __device__ inline float2 recon_combine(const float2* __restrict__ win, int W2, int rr,
