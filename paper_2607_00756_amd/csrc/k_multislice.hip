@@ -58,13 +58,15 @@ __device__ inline void gather_row(const float2 (&v)[16], int t, int y, int col, 
 template <int NX, int FLAGS>
 __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, int ny,
                                                   const float2* __restrict__ T,
-                                                  const float2* __restrict__ tw, int L,
+                                                  const float2* __restrict__ twg, int L,
                                                   const int2* __restrict__ parents, int sign,
                                                   GatherArgs ga, int gb, int ge, int col0,
                                                   float2* __restrict__ save) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
+  __shared__ float2 tw[1024];  // twiddle table: the transforms' barriers order the fill
   __shared__ GatherRec srec[(FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) ? GREC_LDS : 1];
+  for (int i = threadIdx.x; i < L; i += 256) tw[i] = twg[i];
   if constexpr ((FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) != 0) {
     // the plane's records are loaded before the state so that their latency
     // overlaps; the FFT's barriers order them before the gather reads them
@@ -141,14 +143,16 @@ __device__ inline void inject_row(float2 (&v)[16], int t, int y, int col, int ny
 template <int NX, int FLAGS>
 __global__ __launch_bounds__(256) void k_row_adjoint(float2* __restrict__ state, int ny, int ncols,
                                                      const float2* __restrict__ T,
-                                                     const float2* __restrict__ tw, int L,
+                                                     const float2* __restrict__ twg, int L,
                                                      GatherArgs inj, int gb, int ge, int col0,
                                                      const float2* __restrict__ ckpt,
                                                      float two_sigma, float* __restrict__ dv_partial) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
   __shared__ GatherRec srec[GREC_LDS];
+  __shared__ float2 tw[1024];
   if ((int)threadIdx.x < ge - gb && threadIdx.x < GREC_LDS) srec[threadIdx.x] = inj.rec[gb + threadIdx.x];
+  for (int i = threadIdx.x; i < L; i += 256) tw[i] = twg[i];
   __syncthreads();
   const int t = threadIdx.x % S::T;
   const int f = threadIdx.x / S::T;
@@ -213,9 +217,11 @@ struct ColShape {
 template <int NY>
 __global__ __launch_bounds__(ColShape<NY>::THREADS) void k_col_pass(
     float2* __restrict__ state, int nx, const float2* __restrict__ prop,
-    const float2* __restrict__ tw, int L) {
+    const float2* __restrict__ twg, int L) {
   using S = ColShape<NY>;
   __shared__ float2 lds[S::CB * NY];
+  __shared__ float2 tw[1024];  // twiddle table: the transforms' barriers order the fill
+  for (int i = threadIdx.x; i < L; i += S::THREADS) tw[i] = twg[i];
   const int c = threadIdx.x % S::CB;
   const int t = threadIdx.x / S::CB;
   const int x = blockIdx.x * S::CB + c;
