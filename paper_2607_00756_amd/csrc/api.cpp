@@ -275,6 +275,34 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   std::vector<float> ew1, ew2;
   ell(p->rp1, p->col1, p->w1, ec1, ew1);
   ell(p->rp2, p->col2, p->w2, ec2, ew2);
+  // per tile of TILE_B consecutive beams: its distinct parents, and each
+  // beam's padded slots as indices into that list
+  auto tiles = [](const std::vector<int32_t>& rp, const std::vector<int32_t>& ec,
+                  std::vector<int32_t>& ts, std::vector<int32_t>& tp, std::vector<int32_t>& el) {
+    const int nb = (int)rp.size() - 1;
+    const int nt = (nb + TILE_B - 1) / TILE_B;
+    ts.assign(nt + 1, 0);
+    tp.clear();
+    el.assign((size_t)nb * ELL_W, 0);
+    for (int t = 0; t < nt; ++t) {
+      std::vector<int32_t> ps;
+      for (int b = t * TILE_B; b < std::min(nb, (t + 1) * TILE_B); ++b)
+        for (int j = 0; j < std::min(ELL_K, rp[b + 1] - rp[b]); ++j) ps.push_back(ec[(size_t)b * ELL_W + j]);
+      std::sort(ps.begin(), ps.end());
+      ps.erase(std::unique(ps.begin(), ps.end()), ps.end());
+      for (int b = t * TILE_B; b < std::min(nb, (t + 1) * TILE_B); ++b)
+        for (int j = 0; j < ELL_K; ++j) {
+          const int32_t q = ec[(size_t)b * ELL_W + j];
+          const auto it = std::lower_bound(ps.begin(), ps.end(), q);
+          el[(size_t)b * ELL_W + j] = (it != ps.end() && *it == q) ? (int32_t)(it - ps.begin()) : 0;
+        }
+      tp.insert(tp.end(), ps.begin(), ps.end());
+      ts[t + 1] = (int32_t)tp.size();
+    }
+  };
+  std::vector<int32_t> ts1, tp1, el1, ts2, tp2, el2;
+  tiles(p->rp1, ec1, ts1, tp1, el1);
+  tiles(p->rp2, ec2, ts2, tp2, el2);
   if ((rc = dalloc(p, &p->d_tw, p->L)) || (rc = dalloc(p, &p->d_prop, G)) ||
       (rc = dalloc(p, &p->d_T, G * g.nz)) || (rc = upload(p, &p->d_beams, as_int2(p->beams), st)) ||
       (rc = upload(p, &p->d_det, as_int2(p->det), st)) ||
@@ -285,6 +313,9 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = upload(p, &p->d_col2, p->col2, st)) || (rc = upload(p, &p->d_w2, w2f, st)) ||
       (rc = upload(p, &p->d_ellc1, ec1, st)) || (rc = upload(p, &p->d_ellw1, ew1, st)) ||
       (rc = upload(p, &p->d_ellc2, ec2, st)) || (rc = upload(p, &p->d_ellw2, ew2, st)) ||
+      (rc = upload(p, &p->d_tstart1, ts1, st)) || (rc = upload(p, &p->d_tpar1, tp1, st)) ||
+      (rc = upload(p, &p->d_eloc1, el1, st)) || (rc = upload(p, &p->d_tstart2, ts2, st)) ||
+      (rc = upload(p, &p->d_tpar2, tp2, st)) || (rc = upload(p, &p->d_eloc2, el2, st)) ||
       (rc = upload(p, &p->d_W, p->W, st)) || (rc = upload(p, &p->d_oy, p->oy, st)) ||
       (rc = upload(p, &p->d_ox, p->ox, st)) || (rc = upload(p, &p->d_off1, p->off1, st)) ||
       (rc = upload(p, &p->d_off2, p->off2, st)) ||

@@ -140,6 +140,8 @@ struct bip_plan {
   float *d_w1 = nullptr, *d_w2 = nullptr;
   int32_t *d_ellc1 = nullptr, *d_ellc2 = nullptr;  // padded CSR rows
   float *d_ellw1 = nullptr, *d_ellw2 = nullptr;
+  int32_t *d_tstart1 = nullptr, *d_tpar1 = nullptr, *d_eloc1 = nullptr;  // 64-beam tiles
+  int32_t *d_tstart2 = nullptr, *d_tpar2 = nullptr, *d_eloc2 = nullptr;
   int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
   int64_t *d_off1 = nullptr, *d_off2 = nullptr;
   bip::GatherRec *d_grec1 = nullptr, *d_grec2 = nullptr;  // gather records in plane order
@@ -229,6 +231,9 @@ struct ReconArgs {
   const float* w;
   const int32_t* ellc;   // padded rows of the CSR [nb][8] (parents, length, start)
   const float* ellw;     // padded weights [nb][8]
+  const int32_t* tstart; // [nb/64 + 1] parents of each 64-beam tile: tpar[tstart[t] ..)
+  const int32_t* tpar;   // distinct parents of the tiles, ascending
+  const int32_t* ell_loc;// [nb][8] slots 0..5 as indices into the tile's parent list
   const int2* beams;     // target beams [nb]
   int nb;                // number of target beams
   int W, oy, ox;         // window

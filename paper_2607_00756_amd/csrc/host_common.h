@@ -125,6 +125,9 @@ inline ReconArgs recon_args(const bip_plan* p, int a, int side) {
   r.w = side == 1 ? p->d_w1 : p->d_w2;
   r.ellc = side == 1 ? p->d_ellc1 : p->d_ellc2;
   r.ellw = side == 1 ? p->d_ellw1 : p->d_ellw2;
+  r.tstart = side == 1 ? p->d_tstart1 : p->d_tstart2;
+  r.tpar = side == 1 ? p->d_tpar1 : p->d_tpar2;
+  r.ell_loc = side == 1 ? p->d_eloc1 : p->d_eloc2;
   r.beams = side == 1 ? p->d_beams : p->d_det;
   r.nb = side == 1 ? p->B : p->ndet;
   r.W = p->W[a];

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
                                                   float2* __restrict__ save) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
-  __shared__ float2 tw[1024];  // twiddle table: the transforms' barriers order the fill
+  extern __shared__ float2 tw[];  // [L] twiddle table: the transforms' barriers order the fill
   __shared__ GatherRec srec[(FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) ? GREC_LDS : 1];
   for (int i = threadIdx.x; i < L; i += 256) tw[i] = twg[i];
   if constexpr ((FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) != 0) {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_row_adjoint(float2* __restrict__ state,
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
   __shared__ GatherRec srec[GREC_LDS];
-  __shared__ float2 tw[1024];
+  extern __shared__ float2 tw[];  // [L]
   if ((int)threadIdx.x < ge - gb && threadIdx.x < GREC_LDS) srec[threadIdx.x] = inj.rec[gb + threadIdx.x];
   for (int i = threadIdx.x; i < L; i += 256) tw[i] = twg[i];
   __syncthreads();
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(ColShape<NY>::THREADS) void k_col_pass(
     const float2* __restrict__ twg, int L) {
   using S = ColShape<NY>;
   __shared__ float2 lds[S::CB * NY];
-  __shared__ float2 tw[1024];  // twiddle table: the transforms' barriers order the fill
+  extern __shared__ float2 tw[];  // [L] twiddle table: the transforms' barriers order the fill
   for (int i = threadIdx.x; i < L; i += S::THREADS) tw[i] = twg[i];
   const int c = threadIdx.x % S::CB;
   const int t = threadIdx.x / S::CB;
@@ -244,7 +244,7 @@ hipError_t row_launch(float2* state, int ncols, int ny, const float2* T, const f
                       int col0, float2* save, hipStream_t s) {
   using S = RowShape<NX>;
   dim3 grid(ny / S::ROWS, ncols);
-  hipLaunchKernelGGL((k_row_pass<NX, FLAGS>), grid, dim3(256), 0, s, state, ny, T, tw, L, parents,
+  hipLaunchKernelGGL((k_row_pass<NX, FLAGS>), grid, dim3(256), L * sizeof(float2), s, state, ny, T, tw, L, parents,
                      sign, ga, gb, ge, col0, save);
   return hipGetLastError();
 }
@@ -282,7 +282,7 @@ hipError_t adj_launch(float2* state, int ncols, int ny, const float2* T, const f
                       const GatherArgs& inj, int gb, int ge, int col0, const float2* ckpt,
                       float two_sigma, float* dv_partial, int groups, hipStream_t s) {
   using S = RowShape<NX>;
-  hipLaunchKernelGGL((k_row_adjoint<NX, FLAGS>), dim3(ny / S::ROWS, groups), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_row_adjoint<NX, FLAGS>), dim3(ny / S::ROWS, groups), dim3(256), L * sizeof(float2), s,
                      state, ny, ncols, T, tw, L, inj, gb, ge, col0, ckpt, two_sigma, dv_partial);
   return hipGetLastError();
 }
@@ -356,7 +356,7 @@ hipError_t launch_col_pass(float2* state, int ncols, int ny, int nx, const float
   case N: {                                                                          \
     using S = ColShape<N>;                                                           \
     if (nx % S::CB) return hipErrorInvalidValue;                                     \
-    hipLaunchKernelGGL(k_col_pass<N>, dim3(nx / S::CB, ncols), dim3(S::THREADS), 0, s, \
+    hipLaunchKernelGGL(k_col_pass<N>, dim3(nx / S::CB, ncols), dim3(S::THREADS), L * sizeof(float2), s, \
                        state, nx, prop, tw, L);                                      \
     return hipGetLastError();                                                        \
   }

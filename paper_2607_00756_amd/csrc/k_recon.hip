@@ -25,13 +25,9 @@ __device__ inline float2 recon_value(const ReconArgs& a, int b, int r) {
     const float w = a.w[k];
     z.x += w * D.x;
     z.y += w * D.y;
-    m += w * sqrtf(D.x * D.x + D.y * D.y);
+    m += w * habs(D);
   }
-  float2 s = z;
-  if (a.mode == BIP_RECON_MAGNITUDE) {
-    const float az = sqrtf(z.x * z.x + z.y * z.y);
-    s = az > 0.f ? cscale(z, m / az) : make_float2(0.f, 0.f);
-  }
+  const float2 s = a.mode == BIP_RECON_MAGNITUDE ? mag_rescale(z, m) : z;
   const int ry = r / a.W, rx = r - ry * a.W;
   const int y = (a.oy + ry) & (a.ny - 1);
   const int x = (a.ox + rx) & (a.nx - 1);
@@ -50,98 +46,177 @@ __global__ void k_recon_plain(ReconArgs a, float2* out) {
   out[i] = recon_value(a, b, r);
 }
 
-// GEMM operand output, one 64-beam x 32-pixel tile per workgroup.
+// GEMM operand output, one tile of 64 beams per workgroup, 32 pixels at a time.
 // kind 0: S2~^T for the Gram matrix, K-blocked: element (r, b) at
 //         ((b / KB) nrows + r) KB + b mod KB, KB = beams per 64-byte row of a
 //         plane, so each 64-byte column block is contiguous (ld unused)
 // kind 1: element (b, r) at b*ld + r  (r fastest; S2~ for the detector contraction)
-// Each half-wave computes one beam on 32 consecutive pixels, so every parent
-// read is a coalesced 256-byte row segment; the padded weight rows of the
-// tile's beams are staged in LDS first and the parent reads of a value are
-// issued together.  Kind 0 transposes through LDS so that each stored row holds
+// The distinct parents of the tile's 64 beams (at most 64 for square-lattice
+// parents) are staged in LDS, 32 pixels at a time, with coalesced 256-byte
+// reads; the slab of the next 32 pixels is loaded into registers while the
+// current one is combined, so every parent value is read from memory once and
+// the weights are staged once per tile.  Each half-wave combines one beam on
+// 32 consecutive pixels from LDS.  Kind 0 transposes through LDS so that each stored row holds
 // 64 consecutive beams.  The small LDS footprint (~21 KB) keeps 7 workgroups
 // per CU resident to hide the read latency.  Rows and columns beyond the beams
 // or the window are written as zeros.
-constexpr int TB = 64, TR = 32;
+constexpr int TB = TILE_B, TR = 32;
 
 template <int PREC, int KIND>
 __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, int64_t ld,
-                                                       int nrows, int ncols, int64_t plane) {
+                                                       int nrows, int ncols, int64_t plane, int rpw) {
   __shared__ float2 tile[TB][TR + 1];
+  __shared__ float2 sP[TILE_NP][TR];  // the tile's parent windows on the current 32 pixels
+  __shared__ float sM[TILE_NP][TR];   // and their magnitudes
+  extern __shared__ float2 s_tw[];    // exp(-2 pi i k/L), L entries
   __shared__ int s_ec[TB][ELL_W];
   __shared__ float s_ew[TB][ELL_W];
   __shared__ int2 s_h[TB];
+  constexpr int NPF = TILE_NP * TR / 256;  // slab elements per thread
   const int n_b = KIND == 0 ? ncols : nrows;  // beams to write (padded)
   const int n_r = KIND == 0 ? nrows : ncols;  // pixels to write (padded)
   const int nbt = (n_b + TB - 1) / TB, nrt = (n_r + TR - 1) / TR;
-  const int nt = nbt * nrt;
-  // workgroup i runs on XCD i mod 8: give each XCD a contiguous range of beam
-  // tiles so that the parents it reads stay in its L2
+  // one workgroup per beam tile and run of rpw pixel tiles.  Workgroup i runs
+  // on XCD i mod 8: each XCD takes a contiguous range of (run, beam tile)
+  // pairs, neighbouring beam tiles on the same pixels, so that the parents
+  // they share stay in its L2
+  const int nch = (nrt + rpw - 1) / rpw;
   const int per = (int)(gridDim.x / 8);
-  const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (t >= nt) return;
-  const int b0 = (t / nrt) * TB, r0 = (t % nrt) * TR;
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= nbt * nch) return;
+  const int bt = lin % nbt, ch = lin / nbt;
+  const int rt_lo = ch * rpw, rt_hi = min(nrt, rt_lo + rpw);
+  const int b0 = bt * TB;
+  const int W2 = a.W * a.W;
+  // the tile's distinct parents are staged in LDS when they fit (always, for
+  // square-lattice parents); otherwise the parent reads go to memory
+  int ts = 0, n_t = 0;
+  if (b0 < a.nb) {
+    ts = a.tstart[bt];
+    n_t = a.tstart[bt + 1] - ts;
+  }
+  const bool fast = n_t <= TILE_NP;
   for (int i = threadIdx.x; i < TB * ELL_W; i += 256) {
     const int bl = i / ELL_W, j = i % ELL_W;
+    const int64_t e = (int64_t)(b0 + bl) * ELL_W + j;
     const bool in = b0 + bl < a.nb;
-    s_ec[bl][j] = in ? a.ellc[(int64_t)(b0 + bl) * ELL_W + j] : 0;
-    s_ew[bl][j] = in ? a.ellw[(int64_t)(b0 + bl) * ELL_W + j] : 0.f;
+    s_ec[bl][j] = in ? ((fast && j < ELL_K) ? a.ell_loc[e] : a.ellc[e]) : 0;
+    s_ew[bl][j] = in ? a.ellw[e] : 0.f;
   }
   if (threadIdx.x < TB) s_h[threadIdx.x] = b0 + (int)threadIdx.x < a.nb ? a.beams[b0 + threadIdx.x] : make_int2(0, 0);
+  for (int i = threadIdx.x; i < a.L; i += 256) s_tw[i] = a.tw[i];
+  // parent slab of pixel tile rt: element i = (parent pi = i / TR, pixel i % TR)
+  int prow[NPF];
+#pragma unroll
+  for (int q = 0; q < NPF; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    prow[q] = (fast && i < n_t * TR) ? a.tpar[ts + i / TR] : -1;
+  }
+  float2 pre[NPF];
+  auto load_slab = [&](int rt) {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int r = rt * TR + ((threadIdx.x + 256 * q) % TR);
+      pre[q] = (prow[q] >= 0 && r < W2) ? a.win[(int64_t)prow[q] * W2 + r] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_slab = [&]() {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < n_t * TR) {
+        sP[i / TR][i % TR] = pre[q];
+        sM[i / TR][i % TR] = habs(pre[q]);
+      }
+    }
+  };
+  load_slab(rt_lo);
+  store_slab();
+  if (rt_lo + 1 < rt_hi) load_slab(rt_lo + 1);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5, px32 = lane & 31;
-  const int W2 = a.W * a.W;
-  const int r = r0 + px32;
-  const bool live = r < W2;
-  const int rr = live ? r : 0;
-  const int ry = rr / a.W, rx = rr - ry * a.W;
-  const int py = ((a.oy + ry) & (a.ny - 1)) * (a.L / a.ny);
-  const int px = ((a.ox + rx) & (a.nx - 1)) * (a.L / a.nx);
-  __syncthreads();
-  // four beams per batch: all their parent and carrier reads are issued
-  // before any of them is combined
-  constexpr int NBATCH = 4;
-  for (int k0 = 0; k0 < TB / 8; k0 += NBATCH) {
-    float2 D[NBATCH][ELL_K], tw[NBATCH];
-#pragma unroll
-    for (int i = 0; i < NBATCH; ++i) {
-      const int bl = 2 * wave + half + 8 * (k0 + i);
-      const int2 h = s_h[bl];
-      tw[i] = a.tw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
-      recon_load(a.win, W2, rr, s_ec[bl], D[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < NBATCH; ++i) {
-      const int bl = 2 * wave + half + 8 * (k0 + i);
-      const float2 s = recon_finish(D[i], a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
-      float2 v = make_float2(0.f, 0.f);
-      if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(s, tw[i]) : cmul(s, tw[i]);
-      tile[bl][px32] = v;
-    }
-  }
-  __syncthreads();
-  if (KIND == 0) {  // rows r0 + j (8 per wave), 64 consecutive beams per row, K-blocked
-    constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
+  for (int rt = rt_lo; rt < rt_hi; ++rt) {
+    const int r0 = rt * TR;
+    const int r = r0 + px32;
+    const bool live = r < W2;
+    const int rr = live ? r : 0;
+    const int ry = rr / a.W, rx = rr - ry * a.W;
+    const int py = ((a.oy + ry) & (a.ny - 1)) * (a.L / a.ny);
+    const int px = ((a.ox + rx) & (a.nx - 1)) * (a.L / a.nx);
+    if (fast) {
+      // parent values and magnitudes from the slab
 #pragma unroll 2
-    for (int k = 0; k < TR / 4; ++k) {
-      const int j = wave + 4 * k;
-      const int ro = r0 + j, bo = b0 + lane;
-      if (ro < n_r && bo < n_b) {
-        const float2 v = tile[lane][j];
-        store_planes<PREC>(out, ((int64_t)(bo / KB) * n_r + ro) * KB + bo % KB, plane, v.x, v.y);
+      for (int k = 0; k < TB / 8; ++k) {
+        const int bl = 2 * wave + half + 8 * k;
+        const int2 h = s_h[bl];
+        const float2 tw = s_tw[(h.x * py + h.y * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
+        float2 z = make_float2(0.f, 0.f);
+        float m = 0.f;
+#pragma unroll
+        for (int j = 0; j < ELL_K; ++j) {
+          const int c = s_ec[bl][j];
+          const float wj = s_ew[bl][j];
+          const float2 d = sP[c][px32];
+          z.x += wj * d.x;
+          z.y += wj * d.y;
+          m += wj * sM[c][px32];
+        }
+        recon_tail(z, m, a.win, W2, rr, s_ec[bl], a.col, a.w);
+        const float2 sv = a.mode == BIP_RECON_MAGNITUDE ? mag_rescale(z, m) : z;
+        float2 v = make_float2(0.f, 0.f);
+        if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw);
+        tile[bl][px32] = v;
+      }
+    } else {
+      // four beams per batch: all their parent reads are issued before any of
+      // them is combined
+      constexpr int NBATCH = 4;
+      for (int k0 = 0; k0 < TB / 8; k0 += NBATCH) {
+        float2 D[NBATCH][ELL_K];
+#pragma unroll
+        for (int i = 0; i < NBATCH; ++i) recon_load(a.win, W2, rr, s_ec[2 * wave + half + 8 * (k0 + i)], D[i]);
+#pragma unroll
+        for (int i = 0; i < NBATCH; ++i) {
+          const int bl = 2 * wave + half + 8 * (k0 + i);
+          const int2 h = s_h[bl];
+          const float2 tw = s_tw[(h.x * py + h.y * px) & (a.L - 1)];
+          const float2 sv = recon_finish(D[i], a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
+          float2 v = make_float2(0.f, 0.f);
+          if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw);
+          tile[bl][px32] = v;
+        }
       }
     }
-  } else {  // rows b0 + j, 32 consecutive pixels per half-wave
+    __syncthreads();  // tile complete, slab of rt consumed
+    if (rt + 1 < rt_hi) {
+      store_slab();                        // slab rt + 1, loaded during the compute of rt
+      if (rt + 2 < rt_hi) load_slab(rt + 2);
+    }
+    if (KIND == 0) {  // rows r0 + j (8 per wave), 64 consecutive beams per row, K-blocked
+      constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
 #pragma unroll 2
-    for (int k = 0; k < TB / 8; ++k) {
-      const int j = 2 * wave + half + 8 * k;
-      const int bo = b0 + j, ro = r0 + px32;
-      if (bo < n_b && ro < n_r) {
-        const float2 v = tile[j][px32];
-        store_planes<PREC>(out, (int64_t)bo * ld + ro, plane, v.x, v.y);
+      for (int k = 0; k < TR / 4; ++k) {
+        const int j = wave + 4 * k;
+        const int ro = r0 + j, bo = b0 + lane;
+        if (ro < n_r && bo < n_b) {
+          const float2 v = tile[lane][j];
+          store_planes<PREC>(out, ((int64_t)(bo / KB) * n_r + ro) * KB + bo % KB, plane, v.x, v.y);
+        }
+      }
+    } else {  // rows b0 + j, 32 consecutive pixels per half-wave
+#pragma unroll 2
+      for (int k = 0; k < TB / 8; ++k) {
+        const int j = 2 * wave + half + 8 * k;
+        const int bo = b0 + j, ro = r0 + px32;
+        if (bo < n_b && ro < n_r) {
+          const float2 v = tile[j][px32];
+          store_planes<PREC>(out, (int64_t)bo * ld + ro, plane, v.x, v.y);
+        }
       }
     }
+    __syncthreads();  // tile read out, next slab visible
   }
 }
 
@@ -160,14 +235,19 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
   if (nrows_pad <= 0 || ncols_pad <= 0) return hipSuccess;
   if (nrows_pad > INT32_MAX || ncols_pad > INT32_MAX) return hipErrorInvalidValue;
   const int64_t n_b = kind == 0 ? ncols_pad : nrows_pad, n_r = kind == 0 ? nrows_pad : ncols_pad;
-  const int64_t nt = ((n_b + TB - 1) / TB) * ((n_r + TR - 1) / TR);
+  const int64_t nbt = (n_b + TB - 1) / TB, nrt = (n_r + TR - 1) / TR;
+  // runs of pixel tiles long enough to reuse the staged weights, short
+  // enough that the launch still has about 2048 workgroups
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(nrt, (2048 + nbt - 1) / nbt));
+  const int64_t rpw = (nrt + nch - 1) / nch;
+  const int64_t nt = nbt * ((nrt + rpw - 1) / rpw);
   const int64_t nblk = (nt + 7) / 8 * 8;
   if (nblk > INT32_MAX) return hipErrorInvalidValue;
   dim3 grid((unsigned)nblk), block(256);
 #define RC(P, K)                                                                            \
   if (prec == P && kind == K) {                                                             \
-    hipLaunchKernelGGL((k_recon_operand<P, K>), grid, block, 0, s, a, out, ld, (int)nrows_pad, \
-                       (int)ncols_pad, plane_stride);                                       \
+    hipLaunchKernelGGL((k_recon_operand<P, K>), grid, block, a.L * sizeof(float2), s, a, out, ld, (int)nrows_pad, \
+                       (int)ncols_pad, plane_stride, (int)rpw);                             \
     return hipGetLastError();                                                               \
   }
   RC(BIP_PREC_FP32, 0)
