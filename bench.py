@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--precision", default="split", choices=list(PREC))
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the timing of the map-loss gradient on the differentiation specimen")
     ap.add_argument("--map-direct", action="store_true",
                     help="map through the per-beam detector contraction instead of the Gram form")
     ap.add_argument("--compare", action="store_true",
@@ -122,6 +124,62 @@ def cpu_baseline(sp):
                    f"1/{step2} of the scans x{step2} x {n_atoms} atoms; extrapolated full-job time "
                    f"{t_full:.0f} s"),
     }
+
+
+def gradient_leg(steps, warmup):
+    """Forward map + map-loss gradient (dL/dV and dL/dxyz of every atom) on the
+    differentiation specimen: 256^2 grid, 30 slices, 200 keV, 20 mrad, s = 4,
+    16 ionized atoms x 3 channels, scan 48 x 48.  One step is the potential
+    build from the positions, the forward sweeps with slice checkpoints, the
+    FP32 map, the backward (contraction, reconstruction and sweep adjoints) and
+    the position gradient reduction; host wall time around synchronized steps."""
+    import torch
+    from paper_2607_00756_amd import bip, specimen
+
+    dev = torch.device("cuda:0")
+    sp = specimen.make(4)
+    cfg = sp.cfg
+    plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin, ckpt_stride=1)
+    grid = bip.BipGrid(cfg.ny, cfg.nx, cfg.nz, cfg.ly, cfg.lx, cfg.dz)
+    amps = np.array(specimen.POT_AMPS)[None, :] * np.where(sp.species == 1, cfg.species_b_scale, 1.0)[:, None]
+    widths = np.array(specimen.POT_WIDTHS)
+    H = torch.from_numpy(sp.H).to(dev)
+    P = cfg.scan[0] * cfg.scan[1]
+    I = torch.empty(P, dtype=torch.float32, device=dev)
+    V = torch.empty((cfg.nz, cfg.ny, cfg.nx), dtype=torch.float32, device=dev)
+    dV = torch.empty_like(V)
+    It = torch.from_numpy(np.random.default_rng(7).uniform(0.5, 1.5, P)).float().to(dev)
+    marks = {}
+
+    def step():
+        bip.potential_build(grid, sp.xyz, amps, widths, V)
+        plan.build_smatrix(V)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, bip.PREC_FP32, I)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        marks["fwd"] = e
+        plan.eels_backward(sp.n_ch, H, sp.H_off, cfg.scan, (2.0 * (I - It * I.mean())).contiguous(), dV)
+        return bip.potential_grad(grid, sp.xyz, amps, widths, dV)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    fwd_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        torch.cuda.synchronize()
+        fwd_ms += e0.elapsed_time(marks["fwd"])
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n_atoms = len(sp.tau)
+    plan.close()
+    return {"workload": f"{cfg.name}: FCC, {cfg.ny}^2 grid, {cfg.nz} slices, {cfg.energy_ev/1e3:.0f} keV, "
+                        f"{cfg.alpha*1e3:.0f} mrad, s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
+                        f"scan {cfg.scan[0]}x{cfg.scan[1]}, {len(sp.xyz)} atoms in the potential",
+            "ms_per_gradient": ms, "ms_forward": fwd_ms / steps, "ms_backward": ms - fwd_ms / steps,
+            "steps": steps, "outputs": "dL/dV [nz, ny, nx] and dL/dxyz of every atom (FP32 map, FP64 reductions)"}
 
 
 def measured_traffic(stage):
@@ -284,10 +342,12 @@ def main():
             other[name] = {"ms_per_step": dt * 1e3,
                            "rel_l2_vs_" + args.precision: float(torch.linalg.norm(o2 - ref) / torch.linalg.norm(ref))}
         res["other_precisions"] = other
+    plan.close()
+    if not args.no_grad:
+        res["gradient"] = gradient_leg(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sp)
     print(json.dumps(res))
-    plan.close()
 
 
 if __name__ == "__main__":
