@@ -29,10 +29,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "split": 2500.0, "bf16": 2500.0}  # dense MFMA, MI355X
+PEAK_TFLOPS = {"fp32": 157.3, "split": 2500.0, "bf16": 2500.0, "fp16": 2500.0}  # dense MFMA, MI355X
 ALU_PEAK_TFLOPS = 157.3   # FP32 vector FMA, 256 CUs at 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-PREC = {"fp32": 0, "split": 1, "bf16": 2}
+PREC = {"fp32": 0, "split": 1, "bf16": 2, "fp16": 3}
 
 
 def parse():
@@ -255,7 +255,14 @@ def main():
     B, nd = plan.B, plan.ndet
     Sy, Sx = cfg.scan
     G = cfg.ny * cfg.nx
-    csz = 4 if args.precision == "bf16" else 8
+    # bytes per complex element of the S2~ operand: the Gram path stores it in
+    # fp16 for the split precision
+    if args.precision == "fp32":
+        csz = 8
+    elif args.precision == "split":
+        csz = 8 if args.map_direct else 4
+    else:
+        csz = 4
     mfma_peak = PEAK_TFLOPS[args.precision]
     work = {
         # fold (fused S1~ reconstruction, not counted) + DFT over x, then DFT over y
@@ -305,7 +312,8 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "c64 multislice + fp32 MFMA contraction",
                   "split": "c64 multislice + bf16 hi/lo split MFMA contraction (f32 accumulate)",
-                  "bf16": "c64 multislice + bf16 MFMA contraction (f32 accumulate)"}[args.precision],
+                  "bf16": "c64 multislice + bf16 MFMA contraction (f32 accumulate)",
+                  "fp16": "c64 multislice + fp16 MFMA contraction (f32 accumulate)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: FCC 40x40x100 A, {cfg.ny}^2 grid, {cfg.nz} slices, "
                                f"{cfg.energy_ev/1e3:.0f} keV, {cfg.alpha*1e3:.0f}/{cfg.theta*1e3:.0f} mrad, "

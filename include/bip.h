@@ -51,7 +51,7 @@ enum {
 
 enum { BIP_RECON_MAGNITUDE = 0, BIP_RECON_COMPLEX = 1 };
 enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2, BIP_OUT_MAP_DIRECT = 3 };
-enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2 };
+enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2, BIP_PREC_FP16 = 3 };
 
 typedef struct bip_grid {
   int32_t ny, nx, nz;   /* pixels (powers of two, 64..1024) and slice count */
@@ -141,7 +141,12 @@ int bip_reconstruct_local(bip_plan* plan, int32_t atom, float* s1_out, float* s2
  *                (h_x resolved, bin h_x + floor(theta L_x / lambda));
  *                BIP_OUT_BEAMS: f32 [P][n_det] (detector order of bip_query).
  *   precision    BIP_PREC_FP32 (FP32 MFMA), BIP_PREC_SPLIT_BF16 (hi+lo
- *                bf16 products, FP32 accumulate) or BIP_PREC_BF16.
+ *                bf16 products, FP32 accumulate), BIP_PREC_BF16 or
+ *                BIP_PREC_FP16 (one bf16 / fp16 product, FP32 accumulate).
+ *                fp16 operands hold |values| up to 65504: the probe (unit
+ *                norm) and S2 (|G_rr'| <= 1) fit for any input; the Gram
+ *                operand Q needs n_ch * max|H|^2 below 65504 (overflow gives
+ *                inf in the output).
  *   out          device f32, overwritten.
  * Probe coefficients are c_b = 1/sqrt(G B) (unit-norm probe, no aberrations).
  * The probe sum over beams is evaluated exactly as a fold of the beams by

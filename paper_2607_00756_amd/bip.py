@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
 OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT = 0, 1, 2, 3
-PREC_FP32, PREC_SPLIT_BF16, PREC_BF16 = 0, 1, 2
+PREC_FP32, PREC_SPLIT_BF16, PREC_BF16, PREC_FP16 = 0, 1, 2, 3
 Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
     Q_SCALARS = range(9)
 

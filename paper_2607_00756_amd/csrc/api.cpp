@@ -303,6 +303,8 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   std::vector<int32_t> ts1, tp1, el1, ts2, tp2, el2;
   tiles(p->rp1, ec1, ts1, tp1, el1);
   tiles(p->rp2, ec2, ts2, tp2, el2);
+  for (size_t t = 0; t + 1 < ts1.size(); ++t) p->tile_np1 = std::max(p->tile_np1, ts1[t + 1] - ts1[t]);
+  for (size_t t = 0; t + 1 < ts2.size(); ++t) p->tile_np2 = std::max(p->tile_np2, ts2[t + 1] - ts2[t]);
   if ((rc = dalloc(p, &p->d_tw, p->L)) || (rc = dalloc(p, &p->d_prop, G)) ||
       (rc = dalloc(p, &p->d_T, G * g.nz)) || (rc = upload(p, &p->d_beams, as_int2(p->beams), st)) ||
       (rc = upload(p, &p->d_det, as_int2(p->det), st)) ||
@@ -444,7 +446,8 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS &&
       out_mode != BIP_OUT_MAP_DIRECT)
     return err(BIP_EINVAL, "unknown out_mode");
-  if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16)
+  if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16 &&
+      precision != BIP_PREC_FP16)
     return err(BIP_EINVAL, "unknown precision");
   for (int a = 0; a < p->n_atoms; ++a)
     if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
@@ -467,9 +470,16 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   const int64_t Ppad = roundup(P, 128);
   const int64_t Dpad = roundup(p->ndet, 128);  // detector rows (direct path)
   const int64_t Dk = roundup(p->ndet, 32);     // detector as contraction index (Gram path)
-  const int64_t csz = precision == BIP_PREC_BF16 ? 4 : 8;  // bytes per complex element
+  const int64_t csz = (precision == BIP_PREC_BF16 || precision == BIP_PREC_FP16) ? 4 : 8;  // bytes per complex element
   const int planes = precision == BIP_PREC_SPLIT_BF16 ? 4 : 2;
   const int64_t esz = csz / planes;                         // bytes per plane element
+  // The Gram matrix sums |S2~|^2-like products over all n_det detector beams,
+  // which averages the operand rounding: in split mode it runs as single FP16
+  // products (FP32 accumulate), the operand scaled by 2^8 so that its typical
+  // magnitude G^-1/2 ~ 2^-8..2^-10 sits well inside the FP16 normal range; Q is
+  // stored split for the quadratic form, whose rounding does not average.
+  const int gram_prec = precision == BIP_PREC_SPLIT_BF16 ? BIP_PREC_FP16 : precision;
+  const float gram_scale = gram_prec == BIP_PREC_FP16 ? 256.f : 1.f;
   auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };   // padded window pixels
   auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };  // ... to whole tiles
   auto ldf_of = [](int W) { return roundup((int64_t)W * W, 64); };  // DFT workspace pitch
@@ -688,13 +698,15 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
           off[3][i] + s[3] > pl3)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-      if (gram)
+      if (gram) {
+        ReconArgs ra = recon_args(p, a, 2);
+        ra.scale = gram_scale;
         HIPCHK(timed(p, ST_RECON, st, [&] {
-                 return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 0, precision,
-                                             Dk, n1_of(W), Dk, pl1, st);
+                 return launch_recon_operand(ra, S2op + off[1][i] * esz, 0, gram_prec, Dk, n1_of(W), Dk,
+                                             pl1, st);
                }),
                "recon S2 operand");
-      else
+      } else
         HIPCHK(timed(p, ST_RECON, st, [&] {
                  return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 1, precision,
                                              kd_of(W), Dpad, kd_of(W), pl1, st);
@@ -727,8 +739,9 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       q.out = X2;
       q.out_plane = pl2;
       q.tiles = max_n1 / 128;
+      q.gscale = 1.f / (gram_scale * gram_scale);
       HIPCHK(timed(p, ST_GRAM, st, [&] {
-               return launch_zgemm(precision, EPI_GRAMQ, q, (int)gemm_gram_blocks(q.tiles, nat), 1, 1, st);
+               return launch_zgemm_gram(gram_prec, precision, q, (int)gemm_gram_blocks(q.tiles, nat), st);
              }),
              "Gram contraction");
       GemmArgs u = g;

@@ -273,7 +273,8 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     ga.out_plane = n1 * kd;
     ga.out2 = Gm;
     ga.tiles = (int)(n1 / 128);
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_GRAMQ, ga, (int)gemm_gram_blocks(ga.tiles, 1), 1, 1, st), "Gram");
+    ga.gscale = 1.f;
+    HIPCHK(launch_zgemm_gram(BIP_PREC_FP32, BIP_PREC_FP32, ga, (int)gemm_gram_blocks(ga.tiles, 1), st), "Gram");
     // R = conj(psi) diag(Ibar) psi^T over the raster
     HIPCHK(launch_psi_transpose(psiT, Ppad * kdm, (int)kd, W2, P, (int)Ppad, (int)n1, ibar, A1, B1,
                                 n1 * Ppad, st), "psi transpose");

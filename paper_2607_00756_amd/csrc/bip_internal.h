@@ -71,6 +71,7 @@ struct GemmArgs {
   float2* out2;              // EPI_GRAMQ: also store G itself (complex64 [r][r'], pitch ldo)
   const float* rowscale;     // EPI_STORE: optional real factor per output row
   int m_store;               // EPI_STORE: rows >= m_store are not written
+  float gscale;              // EPI_GRAMQ: factor on G (undoes a scaling of the operand), > 0
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {
@@ -142,6 +143,7 @@ struct bip_plan {
   float *d_ellw1 = nullptr, *d_ellw2 = nullptr;
   int32_t *d_tstart1 = nullptr, *d_tpar1 = nullptr, *d_eloc1 = nullptr;  // 64-beam tiles
   int32_t *d_tstart2 = nullptr, *d_tpar2 = nullptr, *d_eloc2 = nullptr;
+  int tile_np1 = 0, tile_np2 = 0;  // most distinct parents of any 64-beam tile
   int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
   int64_t *d_off1 = nullptr, *d_off2 = nullptr;
   bip::GatherRec *d_grec1 = nullptr, *d_grec2 = nullptr;  // gather records in plane order
@@ -234,6 +236,8 @@ struct ReconArgs {
   const int32_t* tstart; // [nb/64 + 1] parents of each 64-beam tile: tpar[tstart[t] ..)
   const int32_t* tpar;   // distinct parents of the tiles, ascending
   const int32_t* ell_loc;// [nb][8] slots 0..5 as indices into the tile's parent list
+  int tile_np;           // most distinct parents of any 64-beam tile
+  float scale;           // factor on the stored operand (exact power of two)
   const int2* beams;     // target beams [nb]
   int nb;                // number of target beams
   int W, oy, ox;         // window
@@ -292,6 +296,8 @@ hipError_t launch_grad_terms(const double* terms, const double* prof, const doub
 // n_tiles, njobs) for EPI_STORE; for EPI_GRAMQ a 1-D grid of gemm_gram_blocks(g.tiles,
 // njobs) workgroups.  epi EPI_STORE + EPI_CONJ_A conjugates the A operand.
 constexpr int EPI_CONJ_A = 16;
+// EPI_GRAMQ: operands in in_prec, Q stored in out_prec (equal, or FP16 -> SPLIT_BF16)
+hipError_t launch_zgemm_gram(int in_prec, int out_prec, const GemmArgs& g, int gx, hipStream_t s);
 hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s);
 int64_t gemm_gram_blocks(int tiles, int njobs);

@@ -128,6 +128,8 @@ inline ReconArgs recon_args(const bip_plan* p, int a, int side) {
   r.tstart = side == 1 ? p->d_tstart1 : p->d_tstart2;
   r.tpar = side == 1 ? p->d_tpar1 : p->d_tpar2;
   r.ell_loc = side == 1 ? p->d_eloc1 : p->d_eloc2;
+  r.tile_np = side == 1 ? p->tile_np1 : p->tile_np2;
+  r.scale = 1.f;
   r.beams = side == 1 ? p->d_beams : p->d_det;
   r.nb = side == 1 ? p->B : p->ndet;
   r.W = p->W[a];

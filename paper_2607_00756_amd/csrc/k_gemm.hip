@@ -7,6 +7,7 @@
 //   SPLIT_BF16  : re_hi, re_lo, im_hi, im_lo       (v_mfma_f32_16x16x32_bf16;
 //                 hi*hi + hi*lo + lo*hi per real product, FP32 accumulate)
 //   BF16        : re, im                          (v_mfma_f32_16x16x32_bf16)
+//   FP16        : re, im                          (v_mfma_f32_16x16x32_f16)
 // A complex product is four real products; the minus sign of re*re - im*im is
 // applied by flipping the sign bit of the A imaginary fragment.
 //
@@ -43,6 +44,7 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 template <int PREC>
@@ -57,6 +59,10 @@ struct PT<BIP_PREC_SPLIT_BF16> {
 };
 template <>
 struct PT<BIP_PREC_BF16> {
+  static constexpr int PLANES = 2, ESZ = 2, BK = 32;
+};
+template <>
+struct PT<BIP_PREC_FP16> {
   static constexpr int PLANES = 2, ESZ = 2, BK = 32;
 };
 
@@ -74,10 +80,11 @@ constexpr int lds_bytes() {
 
 __device__ inline int swz(int row) { return (row >> 2) & 3; }
 
-__device__ inline v8bf neg8(v8bf a) {
+template <typename T>
+__device__ inline T neg8(T a) {  // sign flip of eight 16-bit floats (bf16 or fp16)
   v4u u = __builtin_bit_cast(v4u, a);
   u ^= 0x80008000u;
-  return __builtin_bit_cast(v8bf, u);
+  return __builtin_bit_cast(T, u);
 }
 
 typedef const __attribute__((address_space(1))) void* gptr_t;
@@ -196,6 +203,29 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
         acc.im[bm][bn] = m;
       }
     }
+  } else if constexpr (PREC == BIP_PREC_FP16) {
+    v8h bR[4], bI[4];
+#pragma unroll
+    for (int bn = 0; bn < 4; ++bn) {
+      const int row = wn * 64 + bn * 16 + lr;
+      bR[bn] = lds_frag<v8h>(sB, 0, row, kg);
+      bI[bn] = lds_frag<v8h>(sB, 1, row, kg);
+    }
+#pragma unroll
+    for (int bm = 0; bm < 4; ++bm) {
+      const int row = wm * 64 + bm * 16 + lr;
+      const v8h aR = lds_frag<v8h>(sA, 0, row, kg);
+      const v8h aI = lds_frag<v8h>(sA, 1, row, kg);
+      const v8h nI = neg8(aI);
+      const v8h rI = CONJA ? aI : nI, iI = CONJA ? nI : aI;
+#pragma unroll
+      for (int bn = 0; bn < 4; ++bn) {
+        acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aR, bR[bn], acc.re[bm][bn], 0, 0, 0);
+        acc.re[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rI, bI[bn], acc.re[bm][bn], 0, 0, 0);
+        acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aR, bI[bn], acc.im[bm][bn], 0, 0, 0);
+        acc.im[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x32_f16(iI, bR[bn], acc.im[bm][bn], 0, 0, 0);
+      }
+    }
   } else {
     v8bf bR[4], bI[4];
 #pragma unroll
@@ -250,7 +280,7 @@ __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t ld
 }
 
 // ------------------------------------------------------------- the kernel
-template <int PREC, int EPI, bool CONJA>
+template <int PREC, int EPI, bool CONJA, int OPREC = PREC>
 __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   extern __shared__ char smem[];
   constexpr int ESZ = PT<PREC>::ESZ;
@@ -356,7 +386,7 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int m = m0 + wm * 64 + bm * 16 + kg * 4 + v;
-            const float cr = acc.re[bm][bn][v], ci = acc.im[bm][bn][v];
+            const float cr = g.gscale * acc.re[bm][bn][v], ci = g.gscale * acc.im[bm][bn][v];
             float qr = 0.f, qi = 0.f;
             if (m < job.W2 && n < job.W2) {
               float hr = 0.f, hi = 0.f;
@@ -369,11 +399,11 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
               qr = cr * hr - ci * hi;
               qi = cr * hi + ci * hr;
             }
-            store_planes<PREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
+            store_planes<OPREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
             // Q is Hermitian: the tile below the diagonal is the conjugate transpose
             if (m0 != n0 && m < job.ldo)
-              store_planes<PREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
-                                 -qi);
+              store_planes<OPREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
+                                  -qi);
             if (g.out2) {  // G itself, for the gradient
               const bool in = m < job.W2 && n < job.W2;
               g.out2[job.out_off + (int64_t)m * job.ldo + n] = in ? make_float2(cr, ci) : make_float2(0.f, 0.f);
@@ -463,12 +493,12 @@ __global__ void k_qeels(const float* __restrict__ beams_out, const int32_t* __re
   out[i] = s;
 }
 
-template <int PREC, int EPI, bool CONJA>
+template <int PREC, int EPI, bool CONJA, int OPREC = PREC>
 hipError_t zgemm_launch(const GemmArgs& g, dim3 grid, hipStream_t s) {
-  const void* f = (const void*)k_zgemm<PREC, EPI, CONJA>;
+  const void* f = (const void*)k_zgemm<PREC, EPI, CONJA, OPREC>;
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_zgemm<PREC, EPI, CONJA>), grid, dim3(NTHREADS), lds_bytes<PREC>(), s, g);
+  hipLaunchKernelGGL((k_zgemm<PREC, EPI, CONJA, OPREC>), grid, dim3(NTHREADS), lds_bytes<PREC>(), s, g);
   return hipGetLastError();
 }
 
@@ -477,7 +507,6 @@ hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
   switch (epi) {
     case EPI_ABS2_MAP: return zgemm_launch<PREC, EPI_ABS2_MAP, false>(g, grid, s);
     case EPI_ABS2_BEAMS: return zgemm_launch<PREC, EPI_ABS2_BEAMS, false>(g, grid, s);
-    case EPI_GRAMQ: return zgemm_launch<PREC, EPI_GRAMQ, true>(g, grid, s);
     case EPI_QUAD: return zgemm_launch<PREC, EPI_QUAD, false>(g, grid, s);
     case EPI_STORE: return zgemm_launch<PREC, EPI_STORE, false>(g, grid, s);
     case EPI_STORE + EPI_CONJ_A: return zgemm_launch<PREC, EPI_STORE, true>(g, grid, s);
@@ -487,17 +516,34 @@ hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_zgemm_gram(int in_prec, int out_prec, const GemmArgs& g, int gx, hipStream_t s) {
+  if (gx <= 0 || g.njobs <= 0) return hipSuccess;
+  if (g.tiles <= 0 || gx != gemm_gram_blocks(g.tiles, g.njobs) || !(g.gscale > 0.f))
+    return hipErrorInvalidValue;
+  const dim3 grid(gx, 1, 1);
+  if (in_prec == BIP_PREC_FP16 && out_prec == BIP_PREC_SPLIT_BF16)
+    return zgemm_launch<BIP_PREC_FP16, EPI_GRAMQ, true, BIP_PREC_SPLIT_BF16>(g, grid, s);
+  if (in_prec != out_prec) return hipErrorInvalidValue;
+  switch (in_prec) {
+    case BIP_PREC_FP32: return zgemm_launch<BIP_PREC_FP32, EPI_GRAMQ, true>(g, grid, s);
+    case BIP_PREC_SPLIT_BF16: return zgemm_launch<BIP_PREC_SPLIT_BF16, EPI_GRAMQ, true>(g, grid, s);
+    case BIP_PREC_BF16: return zgemm_launch<BIP_PREC_BF16, EPI_GRAMQ, true>(g, grid, s);
+    case BIP_PREC_FP16: return zgemm_launch<BIP_PREC_FP16, EPI_GRAMQ, true>(g, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s) {
   if (gx <= 0 || gy <= 0 || gz <= 0 || g.njobs <= 0) return hipSuccess;
   if (epi == EPI_QUAD && (g.zsplit != gz || gz > g.njobs)) return hipErrorInvalidValue;
-  if (epi == EPI_GRAMQ && (g.tiles <= 0 || gx != gemm_gram_blocks(g.tiles, g.njobs) || gy != 1 || gz != 1))
-    return hipErrorInvalidValue;
+  if (epi == EPI_GRAMQ) return hipErrorInvalidValue;  // launch_zgemm_gram
   const dim3 grid(gx, gy, gz);
   switch (prec) {
     case BIP_PREC_FP32: return zgemm_prec<BIP_PREC_FP32>(epi, g, grid, s);
     case BIP_PREC_SPLIT_BF16: return zgemm_prec<BIP_PREC_SPLIT_BF16>(epi, g, grid, s);
     case BIP_PREC_BF16: return zgemm_prec<BIP_PREC_BF16>(epi, g, grid, s);
+    case BIP_PREC_FP16: return zgemm_prec<BIP_PREC_FP16>(epi, g, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -257,6 +257,7 @@ hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int
   PY(BIP_PREC_FP32)
   PY(BIP_PREC_SPLIT_BF16)
   PY(BIP_PREC_BF16)
+  PY(BIP_PREC_FP16)
 #undef PY
   return hipErrorInvalidValue;
 }

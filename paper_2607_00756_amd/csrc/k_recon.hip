@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
         recon_tail(z, m, a.win, W2, rr, s_ec[bl], a.col, a.w);
         const float2 sv = a.mode == BIP_RECON_MAGNITUDE ? mag_rescale(z, m) : z;
         float2 v = make_float2(0.f, 0.f);
-        if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw);
+        if (b0 + bl < a.nb && live) v = cscale(a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw), a.scale);
         tile[bl][px32] = v;
       }
     } else {
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
           const float2 tw = s_tw[(h.x * py + h.y * px) & (a.L - 1)];
           const float2 sv = recon_finish(D[i], a.win, W2, rr, s_ec[bl], s_ew[bl], a.col, a.w, a.mode);
           float2 v = make_float2(0.f, 0.f);
-          if (b0 + bl < a.nb && live) v = a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw);
+          if (b0 + bl < a.nb && live) v = cscale(a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw), a.scale);
           tile[bl][px32] = v;
         }
       }
@@ -220,6 +220,125 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
   }
 }
 
+// K-blocked GEMM operand (kind 0) when every 64-beam tile has at most
+// TILE_NP distinct parents: one lane per target beam.  A workgroup owns 64
+// beams and a run of 32-pixel slabs; the slab of the tile's parent windows
+// (values and magnitudes, rows padded to 33 so that lanes on different parents
+// fall in different banks) is staged in LDS, the next one prefetched into
+// registers meanwhile.  Every lane keeps its beam's six slot offsets and
+// weights in registers for the whole run; wave w combines slab pixels
+// 8w .. 8w+7, all lanes on the same pixel, so the slab reads take immediate
+// offsets and the stores of a wave cover 64 consecutive beams of one row.
+constexpr int KR = 33;  // padded LDS row of the slab
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int nrows, int ncols,
+                                                    int64_t plane, int rpw) {
+  __shared__ float2 sP[TILE_NP][KR];
+  __shared__ float sM[TILE_NP][KR];
+  extern __shared__ float2 s_tw[];  // exp(-2 pi i k/L), L entries
+  constexpr int NPF = TILE_NP * TR / 256;
+  constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
+  const int n_b = ncols, n_r = nrows;
+  const int nbt = (n_b + TB - 1) / TB, nrt = (n_r + TR - 1) / TR;
+  const int nch = (nrt + rpw - 1) / rpw;
+  const int per = (int)(gridDim.x / 8);
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= nbt * nch) return;
+  const int bt = lin % nbt, ch = lin / nbt;
+  const int rt_lo = ch * rpw, rt_hi = min(nrt, rt_lo + rpw);
+  const int b0 = bt * TB;
+  const int W2 = a.W * a.W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ts = 0, n_t = 0;
+  if (b0 < a.nb) {
+    ts = a.tstart[bt];
+    n_t = a.tstart[bt + 1] - ts;
+  }
+  for (int i = threadIdx.x; i < a.L; i += 256) s_tw[i] = a.tw[i];
+  // this lane's beam: slot offsets (LDS bytes, including the wave's first
+  // pixel), weights, CSR tail, carrier frequencies
+  const int b = b0 + lane;
+  const bool bvalid = b < a.nb;
+  int oP[ELL_K], oM[ELL_K];
+  float wt[ELL_K];
+  int ec[ELL_W];
+#pragma unroll
+  for (int j = 0; j < ELL_K; ++j) {
+    const int c = bvalid ? a.ell_loc[(int64_t)b * ELL_W + j] : 0;
+    wt[j] = bvalid ? a.ellw[(int64_t)b * ELL_W + j] : 0.f;
+    oP[j] = (c * KR + 8 * wave) * (int)sizeof(float2);
+    oM[j] = (c * KR + 8 * wave) * (int)sizeof(float);
+  }
+  ec[6] = bvalid ? a.ellc[(int64_t)b * ELL_W + 6] : 0;
+  ec[7] = bvalid ? a.ellc[(int64_t)b * ELL_W + 7] : 0;
+  const int2 h = bvalid ? a.beams[b] : make_int2(0, 0);
+  const int ky = h.x * (a.L / a.ny), kx = h.y * (a.L / a.nx);
+  // slab rows: element i = (parent i / TR, pixel i % TR)
+  int prow[NPF];
+#pragma unroll
+  for (int q = 0; q < NPF; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    prow[q] = i < n_t * TR ? a.tpar[ts + i / TR] : -1;
+  }
+  float2 pre[NPF];
+  auto load_slab = [&](int rt) {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int r = rt * TR + ((threadIdx.x + 256 * q) % TR);
+      pre[q] = (prow[q] >= 0 && r < W2) ? a.win[(int64_t)prow[q] * W2 + r] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_slab = [&]() {
+#pragma unroll
+    for (int q = 0; q < NPF; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < n_t * TR) {
+        sP[i / TR][i % TR] = pre[q];
+        sM[i / TR][i % TR] = habs(pre[q]);
+      }
+    }
+  };
+  load_slab(rt_lo);
+  store_slab();
+  if (rt_lo + 1 < rt_hi) load_slab(rt_lo + 1);
+  __syncthreads();
+  const char* sPb = (const char*)&sP[0][0];
+  const char* sMb = (const char*)&sM[0][0];
+  const int64_t ob = (int64_t)(b / KB) * n_r * KB + b % KB;  // this lane's column of the blocks
+  const bool bstore = b < n_b;
+  for (int rt = rt_lo; rt < rt_hi; ++rt) {
+#pragma unroll
+    for (int i = 0; i < TR / 4; ++i) {
+      const int r = rt * TR + 8 * wave + i;  // window pixel (wave-uniform)
+      const int ry = r / a.W, rx = r - ry * a.W;
+      const int py = (a.oy + ry) & (a.ny - 1), px = (a.ox + rx) & (a.nx - 1);
+      float2 z = make_float2(0.f, 0.f);
+      float m = 0.f;
+#pragma unroll
+      for (int j = 0; j < ELL_K; ++j) {
+        const float2 d = *(const float2*)(sPb + oP[j] + i * (int)sizeof(float2));
+        const float dm = *(const float*)(sMb + oM[j] + i * (int)sizeof(float));
+        z.x += wt[j] * d.x;
+        z.y += wt[j] * d.y;
+        m += wt[j] * dm;
+      }
+      if (r < W2) recon_tail(z, m, a.win, W2, r, ec, a.col, a.w);
+      const float2 sv = a.mode == BIP_RECON_MAGNITUDE ? mag_rescale(z, m) : z;
+      const float2 tw = s_tw[(ky * py + kx * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
+      float2 v = cscale(a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw), a.scale);
+      if (!bvalid || r >= W2) v = make_float2(0.f, 0.f);
+      if (bstore && r < n_r) store_planes<PREC>(out, ob + (int64_t)r * KB, plane, v.x, v.y);
+    }
+    __syncthreads();  // slab of rt consumed
+    if (rt + 1 < rt_hi) {
+      store_slab();
+      if (rt + 2 < rt_hi) load_slab(rt + 2);
+    }
+    __syncthreads();  // next slab visible
+  }
+}
+
 }  // namespace
 
 hipError_t launch_recon_plain(const ReconArgs& a, float2* out, hipStream_t s) {
@@ -244,6 +363,20 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
   const int64_t nblk = (nt + 7) / 8 * 8;
   if (nblk > INT32_MAX) return hipErrorInvalidValue;
   dim3 grid((unsigned)nblk), block(256);
+  if (kind == 0 && a.tile_np <= TILE_NP) {
+#define RK(P)                                                                                    \
+  if (prec == P) {                                                                               \
+    hipLaunchKernelGGL((k_recon_kblk<P>), grid, block, a.L * sizeof(float2), s, a, out,          \
+                       (int)nrows_pad, (int)ncols_pad, plane_stride, (int)rpw);                  \
+    return hipGetLastError();                                                                    \
+  }
+    RK(BIP_PREC_FP32)
+    RK(BIP_PREC_SPLIT_BF16)
+    RK(BIP_PREC_BF16)
+    RK(BIP_PREC_FP16)
+#undef RK
+    return hipErrorInvalidValue;
+  }
 #define RC(P, K)                                                                            \
   if (prec == P && kind == K) {                                                             \
     hipLaunchKernelGGL((k_recon_operand<P, K>), grid, block, a.L * sizeof(float2), s, a, out, ld, (int)nrows_pad, \
@@ -256,6 +389,8 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
   RC(BIP_PREC_SPLIT_BF16, 1)
   RC(BIP_PREC_BF16, 0)
   RC(BIP_PREC_BF16, 1)
+  RC(BIP_PREC_FP16, 0)
+  RC(BIP_PREC_FP16, 1)
 #undef RC
   return hipErrorInvalidValue;
 }

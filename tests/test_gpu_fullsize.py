@@ -3,7 +3,8 @@
 bench.py times: the plan holds every atom, the contraction runs for a sample
 of atoms (those ionized in the deepest plane, which keeps the oracle's parent
 sweeps short), and the oracle computes the map at a sample of scan
-positions.  Bar: rel-L2 <= 1e-4 for FP32 and split-BF16."""
+positions.  Bar: rel-L2 <= 1e-4 for FP32 and split; plain FP16 reported
+(bounded at 1e-3)."""
 from __future__ import annotations
 
 import numpy as np
@@ -29,7 +30,7 @@ def c1():
     return sp, atoms, scans, want
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_c1_full_size_map_sampled(c1, prec):
     from paper_2607_00756_amd import bip
     torch, dev = torch_dev()
@@ -44,5 +45,5 @@ def test_c1_full_size_map_sampled(c1, prec):
     got = out.cpu().numpy().astype(np.float64)[scans]
     err = rel_l2(got, want)
     print(f"[c1 full size prec {prec}] map rel-L2 vs FP64 oracle on sampled scans {err:.3e}")
-    assert err < 1e-4
+    assert err < (1e-3 if prec == 3 else 1e-4)
     plan.close()

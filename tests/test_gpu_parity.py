@@ -1,9 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bar: rel-L2 <= 1e-4 for the FP32 and split-BF16 contraction paths (the
-accuracy target of the hot path), parent windows and reconstructions at
+Bar: rel-L2 <= 1e-4 for the FP32 and split contraction paths (the accuracy
+target of the hot path), parent windows and reconstructions at
 <= 1e-5 (complex64 multislice), Sibson weights to 1e-12 (FP64 geometry).
-Plain BF16 is reported with its measured error and only bounded loosely."""
+Plain BF16 and FP16 are reported with their measured errors and only bounded
+loosely (3e-2 and 1e-3)."""
 from __future__ import annotations
 
 import dataclasses
@@ -20,7 +21,7 @@ from tests.gpu_helpers import gpu_run, make_plan, rel_l2, torch_dev
 
 pytestmark = pytest.mark.gpu
 
-FP32, SPLIT, BF16 = 0, 1, 2
+FP32, SPLIT, BF16, FP16 = 0, 1, 2, 3
 MAP, QEELS, BEAMS, MAP_DIRECT = 0, 1, 2, 3
 
 
@@ -108,7 +109,7 @@ def test_c0_reconstruct_local(c0, mode):
     assert e1 < 1e-5 and e2 < 1e-5
 
 
-@pytest.mark.parametrize("prec", [FP32, SPLIT, BF16])
+@pytest.mark.parametrize("prec", [FP32, SPLIT, BF16, FP16])
 @pytest.mark.parametrize("out_mode", [MAP, QEELS, BEAMS, MAP_DIRECT])
 def test_c0_signal(c0, prec, out_mode):
     sp = c0["sp"]
@@ -118,7 +119,7 @@ def test_c0_signal(c0, prec, out_mode):
     err = rel_l2(got, want)
     print(f"[c0 signal prec {prec} mode {out_mode}] rel-L2 vs FP64 oracle {err:.3e}")
     assert got.shape == want.shape
-    assert err < (1e-4 if prec != BF16 else 3e-2)
+    assert err < {FP32: 1e-4, SPLIT: 1e-4, BF16: 3e-2, FP16: 1e-3}[prec]
 
 
 # ----------------------------------------------- ragged multi-atom problems
@@ -130,7 +131,7 @@ def _ragged_problem(s=2, recon=E.RECON_MAGNITUDE):
 
 
 @pytest.mark.parametrize("s", [1, 2, 3])
-@pytest.mark.parametrize("prec", [FP32, SPLIT])
+@pytest.mark.parametrize("prec", [FP32, SPLIT, FP16])
 def test_ragged_windows_and_tiles_map(s, prec):
     """Map through the Gram reordering on ragged windows (W = 4 .. 64)."""
     cfg, tp = _ragged_problem(s)
@@ -140,11 +141,11 @@ def test_ragged_windows_and_tiles_map(s, prec):
                         MAP, prec)
     err = rel_l2(got, want)
     print(f"[ragged map s={s} prec {prec}] rel-L2 {err:.3e}")
-    assert err < 1e-4
+    assert err < (1e-3 if prec == FP16 else 1e-4)
 
 
 @pytest.mark.parametrize("s", [1, 2, 3])
-@pytest.mark.parametrize("prec", [FP32, SPLIT])
+@pytest.mark.parametrize("prec", [FP32, SPLIT, FP16])
 def test_ragged_windows_and_tiles(s, prec):
     cfg, tp = _ragged_problem(s)
     prob = as_oracle_problem(tp)
@@ -154,7 +155,7 @@ def test_ragged_windows_and_tiles(s, prec):
     assert plan.ndet > 256 and plan.ndet % 128 != 0 and plan.B % 32 != 0
     err = rel_l2(got, want)
     print(f"[ragged s={s} prec {prec}] B={plan.B} ndet={plan.ndet} rel-L2 {err:.3e}")
-    assert err < 1e-4
+    assert err < (1e-3 if prec == FP16 else 1e-4)
 
 
 def test_full_window_parent_columns_every_plane():
