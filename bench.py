@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the timing of the map-loss gradient on the differentiation specimen")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only time the map-loss gradient and print its JSON object")
     ap.add_argument("--map-direct", action="store_true",
                     help="map through the per-beam detector contraction instead of the Gram form")
     ap.add_argument("--compare", action="store_true",
@@ -210,6 +212,9 @@ def main():
         return
     if args.column_batch is not None:
         os.environ["BIP_COLUMN_BATCH"] = str(args.column_batch)
+    if args.grad_only:
+        print(json.dumps({"gradient": gradient_leg(args.steps, args.warmup)}))
+        return
     import torch
     from paper_2607_00756_amd import bip, specimen
 

@@ -128,25 +128,25 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
       return rc;
     HIPCHK(hipStreamSynchronize(st), "weight tables");  // the host vectors go out of scope
   }
-  // workspace (one atom at a time, sized for the largest window)
+  // Workspace.  The products of the contraction backward run batched over
+  // chunks of atoms (one launch per product and chunk, grid z or the Gram job
+  // list over the atoms), so that small windows still fill the chip; every
+  // atom of a chunk gets a block sized for the largest window.
   const int nbmax = std::max(p->B, p->ndet);
   const int batch = p->column_batch > 0 ? p->column_batch : std::max(p->Bp1, p->Bp2);
   const int groups = std::min(kAdjGroups, std::max(1, batch));
-  size_t need = 0;
-  auto sz = [&](size_t bytes) { need += (size_t)roundup((int64_t)bytes, 256); };
-  sz((size_t)P * ldfm * 8);        // X / Y
-  sz((size_t)P * ldfm * 8);        // Z
-  sz((size_t)2 * Ppad * kdm * 4);  // psi^T planes
-  sz((size_t)2 * n1m * Dk * 4);    // S2~ K-blocked planes
-  sz((size_t)2 * Dpad * kdm * 4);  // S2~ [d][r] planes
-  sz((size_t)2 * n1m * kdm * 4);   // Q planes
-  sz((size_t)n1m * kdm * 8);       // G
-  sz((size_t)2 * n1m * Ppad * 4);  // A1
-  sz((size_t)2 * n1m * Ppad * 4);  // B1
-  sz((size_t)n1m * kdm * 8);       // R
-  sz((size_t)2 * n1m * kdm * 4);   // K planes
-  sz((size_t)Ppad * kdm * 8);      // g_psi
-  sz((size_t)Dpad * kdm * 8);      // g_S2~
+  const int64_t bX = (int64_t)P * ldfm;  // raster DFT workspace (complex)
+  const int64_t bPsi = Ppad * kdm;       // psi^T [Ppad][kd] (FP32 planes)
+  const int64_t bS2b = n1m * Dk;         // S2~ K-blocked
+  const int64_t bS2d = Dpad * kdm;       // S2~ [d][r]
+  const int64_t bQ = n1m * kdm;          // Q, K (planes); G, R (complex) [n1][kd]
+  const int64_t bA = n1m * Ppad;         // A1, B1 [n1][Ppad] (planes)
+  const int64_t bGp = Ppad * kdm;        // g_psi (complex)
+  const int64_t bGs = Dpad * kdm;        // g_S2~ (complex)
+  const int64_t per_atom = 8 * (bX + bPsi + bS2b + bS2d + 4 * bQ + 2 * bA + bGp + bGs) + 16 * 256;
+  size_t fixed = 0;
+  auto sz = [&](size_t bytes) { fixed += (size_t)roundup((int64_t)bytes, 256); };
+  sz((size_t)bX * 8);              // Z
   sz((size_t)nbmax * W2m * 8);     // g_z
   sz((size_t)nbmax * W2m * 4);     // gamma
   sz((size_t)n_ch * W2m * 8);      // g_H scratch
@@ -156,23 +156,16 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   sz(cells.size() * 4);
   sz(tws.size() * 8);
   sz(jprobe.size() * sizeof(ProbeJob));
-  sz(3 * (size_t)p->n_atoms * sizeof(GemmJob));
-  int rc = ensure_work(p, need + 4096);
+  sz(4 * (size_t)p->n_atoms * sizeof(GemmJob));
+  const char* env = std::getenv("BIP_WORKSPACE_GB");
+  const double budget_gb = env ? std::atof(env) : 24.0;
+  const int64_t budget = (int64_t)(budget_gb * (1 << 30));
+  const int nat_max =
+      (int)std::max<int64_t>(1, std::min<int64_t>(p->n_atoms, (budget - (int64_t)fixed) / per_atom));
+  int rc = ensure_work(p, fixed + (size_t)nat_max * per_atom + 4096);
   if (rc) return rc;
   Workspace ws{(char*)p->d_work, 0};
-  float2* X = (float2*)ws.take((size_t)P * ldfm * 8);
-  float2* Z = (float2*)ws.take((size_t)P * ldfm * 8);
-  float* psiT = (float*)ws.take((size_t)2 * Ppad * kdm * 4);
-  float* S2b = (float*)ws.take((size_t)2 * n1m * Dk * 4);
-  float* S2d = (float*)ws.take((size_t)2 * Dpad * kdm * 4);
-  float* Qp = (float*)ws.take((size_t)2 * n1m * kdm * 4);
-  float2* Gm = (float2*)ws.take((size_t)n1m * kdm * 8);
-  float* A1 = (float*)ws.take((size_t)2 * n1m * Ppad * 4);
-  float* B1 = (float*)ws.take((size_t)2 * n1m * Ppad * 4);
-  float2* R = (float2*)ws.take((size_t)n1m * kdm * 8);
-  float* Kp = (float*)ws.take((size_t)2 * n1m * kdm * 4);
-  float2* gpsi = (float2*)ws.take((size_t)Ppad * kdm * 8);
-  float2* gS2 = (float2*)ws.take((size_t)Dpad * kdm * 8);
+  float2* Z = (float2*)ws.take((size_t)bX * 8);
   float2* gz = (float2*)ws.take((size_t)nbmax * W2m * 8);
   float* gam = (float*)ws.take((size_t)nbmax * W2m * 4);
   float2* gHs = (float2*)ws.take((size_t)n_ch * W2m * 8);
@@ -182,8 +175,26 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   int32_t* d_cells = (int32_t*)ws.take(cells.size() * 4);
   float2* d_tws = (float2*)ws.take(tws.size() * 8);
   ProbeJob* d_probe = (ProbeJob*)ws.take(jprobe.size() * sizeof(ProbeJob));
-  GemmJob* d_jobs = (GemmJob*)ws.take(3 * (size_t)p->n_atoms * sizeof(GemmJob));
+  GemmJob* d_jobs = (GemmJob*)ws.take(4 * (size_t)p->n_atoms * sizeof(GemmJob));
+  const int64_t NA = nat_max;
+  float2* X = (float2*)ws.take((size_t)(NA * bX) * 8);
+  float* psiT = (float*)ws.take((size_t)(2 * NA * bPsi) * 4);
+  float* S2b = (float*)ws.take((size_t)(2 * NA * bS2b) * 4);
+  float* S2d = (float*)ws.take((size_t)(2 * NA * bS2d) * 4);
+  float* Qp = (float*)ws.take((size_t)(2 * NA * bQ) * 4);
+  float2* Gm = (float2*)ws.take((size_t)(NA * bQ) * 8);
+  float* A1 = (float*)ws.take((size_t)(2 * NA * bA) * 4);
+  float* B1 = (float*)ws.take((size_t)(2 * NA * bA) * 4);
+  float2* R = (float2*)ws.take((size_t)(NA * bQ) * 8);
+  float* Kp = (float*)ws.take((size_t)(2 * NA * bQ) * 4);
+  float2* gpsi = (float2*)ws.take((size_t)(NA * bGp) * 8);
+  float2* gS2 = (float2*)ws.take((size_t)(NA * bGs) * 8);
   if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: backward workspace");
+  // the atom's slot in its chunk (chunks are consecutive runs of nat_max atoms)
+  for (int a = 0; a < p->n_atoms; ++a) {
+    jprobe[a].fx_off = (a % nat_max) * bX;
+    jprobe[a].out_off = (a % nat_max) * bPsi;
+  }
   HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
   HIPCHK(hipMemcpyAsync(d_tws, tws.data(), tws.size() * 8, hipMemcpyHostToDevice, st), "twiddles");
   HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
@@ -216,19 +227,23 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   pa.cb = cb;
   pa.fx = X;
   pa.out = psiT;
-  pa.out_plane = Ppad * kdm;
+  pa.out_plane = NA * bPsi;
   pa.H = (const float2*)H;
   pa.n_ch = n_ch;
   const float2* twxc = d_tws + scan_sx + scan_sy;
   const float2* twyc = twxc + scan_sx;
-  // ---------------------------------------------------------- per atom
-  // three products per atom: Gram (G, Q), R, and the two gradient products
+  // four products per atom: Gram (G, Q), R, g_psi and g_S2~, each with the
+  // atom's blocks as operand and output offsets
   std::vector<GemmJob>& hj = p->h_jobs2;
-  hj.assign(3 * (size_t)p->n_atoms, GemmJob{});
-  for (int a = 0; a < p->n_atoms; ++a) {
+  hj.assign(4 * (size_t)p->n_atoms, GemmJob{});
+  const int na = p->n_atoms;
+  for (int a = 0; a < na; ++a) {
+    const int64_t i = a % nat_max;
     const int W2 = p->W[a] * p->W[a];
     const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
-    GemmJob& q = hj[3 * a];
+    GemmJob& q = hj[a];
+    q.a_off = q.b_off = i * bS2b;
+    q.out_off = i * bQ;
     q.K = (int32_t)Dk;
     q.lda = q.ldb = BKF;
     q.kstride = (int32_t)(n1 * BKF);
@@ -236,96 +251,136 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     q.W2 = W2;
     q.ldo = (int32_t)kd;
     q.h_off = H_off[a];
-    GemmJob& rj = hj[3 * a + 1];
+    GemmJob& rj = hj[na + a];
+    rj.a_off = rj.b_off = i * bA;
+    rj.out_off = i * bQ;
     rj.K = rj.lda = rj.ldb = (int32_t)Ppad;
     rj.m_lim = rj.n_lim = W2;
     rj.W2 = W2;
     rj.ldo = (int32_t)kd;
-    GemmJob& uj = hj[3 * a + 2];
-    uj.K = uj.lda = uj.ldb = (int32_t)kd;
-    uj.m_lim = (int32_t)std::max(Ppad, Dpad);
-    uj.n_lim = W2;
-    uj.W2 = W2;
-    uj.ldo = (int32_t)kd;
+    GemmJob& pj = hj[2 * na + a];
+    pj.a_off = i * bPsi;
+    pj.b_off = i * bQ;
+    pj.out_off = i * bGp;
+    pj.K = pj.lda = pj.ldb = (int32_t)kd;
+    pj.m_lim = (int32_t)Ppad;
+    pj.n_lim = W2;
+    pj.W2 = W2;
+    pj.ldo = (int32_t)kd;
+    GemmJob& sj = hj[3 * na + a];
+    sj.a_off = i * bS2d;
+    sj.b_off = i * bQ;
+    sj.out_off = i * bGs;
+    sj.K = sj.lda = sj.ldb = (int32_t)kd;
+    sj.m_lim = (int32_t)Dpad;
+    sj.n_lim = W2;
+    sj.W2 = W2;
+    sj.ldo = (int32_t)kd;
   }
   HIPCHK(hipMemcpyAsync(d_jobs, hj.data(), hj.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
-  for (int a = 0; a < p->n_atoms; ++a) {
-    const int W = p->W[a], W2 = W * W;
-    const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128), ldf = roundup(W2, 64);
-    const float2* Ha = (const float2*)H + H_off[a];
-    GemmJob* jobs_a = d_jobs + 3 * a;
-    // psi^T [rho][r] (FP32), exactly as the forward synthesis
-    pa.jobs = d_probe + a;
-    HIPCHK(launch_probe_fold_x(pa, W2, 1, st), "probe fold");
-    HIPCHK(launch_probe_y(pa, BIP_PREC_FP32, false, (int)kd, 1, st), "probe synthesis");
-    // S2~ K-blocked (Gram) and [d][r] (gradient product), FP32
-    HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2b, 0, BIP_PREC_FP32, Dk, n1, Dk, n1 * Dk, st), "recon S2");
-    HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2d, 1, BIP_PREC_FP32, kd, Dpad, kd, Dpad * kd, st), "recon S2");
+  for (int c0 = 0; c0 < na; c0 += nat_max) {
+    const int nat = std::min(nat_max, na - c0);
+    int max_w2 = 0, max_n1 = 0, max_kd = 0;
+    for (int a = c0; a < c0 + nat; ++a) {
+      const int W2 = p->W[a] * p->W[a];
+      max_w2 = std::max(max_w2, W2);
+      max_n1 = std::max(max_n1, (int)roundup(W2, 128));
+      max_kd = std::max(max_kd, (int)roundup(W2, 32));
+    }
+    // psi^T [rho][r] (FP32) of every atom of the chunk, exactly as the forward synthesis
+    pa.jobs = d_probe + c0;
+    HIPCHK(launch_probe_fold_x(pa, max_w2, nat, st), "probe fold");
+    HIPCHK(launch_probe_y(pa, BIP_PREC_FP32, false, max_kd, nat, st), "probe synthesis");
+    for (int a = c0; a < c0 + nat; ++a) {
+      const int64_t i = a - c0;
+      const int W2 = p->W[a] * p->W[a];
+      const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
+      // S2~ K-blocked (Gram) and [d][r] (gradient product), FP32
+      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2b + i * bS2b, 0, BIP_PREC_FP32, Dk, n1, Dk,
+                                  NA * bS2b, st), "recon S2");
+      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2d + i * bS2d, 1, BIP_PREC_FP32, kd, Dpad, kd,
+                                  NA * bS2d, st), "recon S2");
+      // conj(psi) and Ibar psi as [r][rho] operands of R
+      HIPCHK(launch_psi_transpose(psiT + i * bPsi, NA * bPsi, (int)kd, W2, P, (int)Ppad, (int)n1, ibar,
+                                  A1 + i * bA, B1 + i * bA, NA * bA, st), "psi transpose");
+    }
     // Gram matrix G and Q = G o Hc
     GemmArgs ga{};
     ga.H = (const float2*)H;
     ga.n_ch = n_ch;
     ga.A = ga.B = S2b;
-    ga.a_plane = ga.b_plane = n1 * Dk;
-    ga.jobs = jobs_a;
-    ga.njobs = 1;
+    ga.a_plane = ga.b_plane = NA * bS2b;
+    ga.jobs = d_jobs + c0;
+    ga.njobs = nat;
     ga.out = Qp;
-    ga.out_plane = n1 * kd;
+    ga.out_plane = NA * bQ;
     ga.out2 = Gm;
-    ga.tiles = (int)(n1 / 128);
+    ga.tiles = max_n1 / 128;
     ga.gscale = 1.f;
-    HIPCHK(launch_zgemm_gram(BIP_PREC_FP32, BIP_PREC_FP32, ga, (int)gemm_gram_blocks(ga.tiles, 1), st), "Gram");
+    HIPCHK(launch_zgemm_gram(BIP_PREC_FP32, BIP_PREC_FP32, ga, (int)gemm_gram_blocks(ga.tiles, nat), st), "Gram");
     // R = conj(psi) diag(Ibar) psi^T over the raster
-    HIPCHK(launch_psi_transpose(psiT, Ppad * kdm, (int)kd, W2, P, (int)Ppad, (int)n1, ibar, A1, B1,
-                                n1 * Ppad, st), "psi transpose");
     GemmArgs gr{};
     gr.A = A1;
     gr.B = B1;
-    gr.a_plane = gr.b_plane = n1 * Ppad;
-    gr.jobs = jobs_a + 1;
-    gr.njobs = 1;
+    gr.a_plane = gr.b_plane = NA * bA;
+    gr.jobs = d_jobs + na + c0;
+    gr.njobs = nat;
     gr.out = R;
-    gr.m_store = (int)n1;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE + EPI_CONJ_A, gr, (int)(n1 / 128), (int)(n1 / 128), 1, st), "R");
-    HIPCHK(launch_kmat(R, Ha, n_ch, W2, (int)kd, (int)n1, Kp, n1 * kd, st), "K");
+    gr.m_store = max_n1;
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE + EPI_CONJ_A, gr, max_n1 / 128, max_n1 / 128, nat, st), "R");
+    for (int a = c0; a < c0 + nat; ++a) {
+      const int64_t i = a - c0;
+      const int W2 = p->W[a] * p->W[a];
+      const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
+      HIPCHK(launch_kmat(R + i * bQ, (const float2*)H + H_off[a], n_ch, W2, (int)kd, (int)n1, Kp + i * bQ,
+                         NA * bQ, st), "K");
+    }
     // g_psi = Ibar (Q psi) and g_S2~ = S2~ K^T
     GemmArgs gp{};
     gp.A = psiT;
-    gp.a_plane = Ppad * kdm;
+    gp.a_plane = NA * bPsi;
     gp.B = Qp;
-    gp.b_plane = n1 * kd;
-    gp.jobs = jobs_a + 2;
-    gp.njobs = 1;
+    gp.b_plane = NA * bQ;
+    gp.jobs = d_jobs + 2 * na + c0;
+    gp.njobs = nat;
     gp.out = gpsi;
     gp.rowscale = ibar;
     gp.m_store = (int)Ppad;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gp, (int)(Ppad / 128), (int)(n1 / 128), 1, st), "g_psi");
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gp, (int)(Ppad / 128), max_n1 / 128, nat, st), "g_psi");
     GemmArgs gs{};
     gs.A = S2d;
-    gs.a_plane = Dpad * kd;
+    gs.a_plane = NA * bS2d;
     gs.B = Kp;
-    gs.b_plane = n1 * kd;
-    gs.jobs = jobs_a + 2;
-    gs.njobs = 1;
+    gs.b_plane = NA * bQ;
+    gs.jobs = d_jobs + 3 * na + c0;
+    gs.njobs = nat;
     gs.out = gS2;
     gs.m_store = (int)Dpad;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gs, (int)(Dpad / 128), (int)(n1 / 128), 1, st), "g_S2");
-    // transition-potential cotangent and the position gradient through H
-    float2* gH = dL_dHconj ? (float2*)dL_dHconj + H_off[a] : gHs;
-    HIPCHK(launch_grad_h(Gm, R, Ha, n_ch, W2, (int)kd, gH, st), "g_H");
-    if (dHdx)
-      HIPCHK(launch_grad_tau(gH, (const float2*)dHdx + H_off[a], (const float2*)dHdy + H_off[a],
-                             n_ch * W2, dtau + 2 * a, st), "dtau");
-    // adjoint of the probe sum: Z[a][c][r] = sum_{u,v} exp(+2 pi i (a u/S_y + c v/S_x)) g_psi
-    HIPCHK(launch_dft_pass(gpsi, X, scan_sx, kd, scan_sx * kd, ldf, scan_sx * ldf, scan_sy, W2, twxc, st), "adjoint DFT x");
-    HIPCHK(launch_dft_pass(X, Z, scan_sy, scan_sx * ldf, ldf, scan_sx * ldf, ldf, scan_sx, W2, twyc, st), "adjoint DFT y");
-    // reconstruction adjoints -> window cotangents
-    HIPCHK(launch_recon_adjoint(recon_args(p, a, 1), 1, Z, ldf, scan_sy, scan_sx, cb, gz, gam,
-                                p->d_par1, p->Bp1, p->d_tp1_rp, p->d_tp1_b, p->d_tp1_w,
-                                p->d_gwin1 + p->off1[a], st), "recon adjoint S1");
-    HIPCHK(launch_recon_adjoint(recon_args(p, a, 2), 2, gS2, kd, scan_sy, scan_sx, cb, gz, gam,
-                                p->d_par2, p->Bp2, p->d_tp2_rp, p->d_tp2_b, p->d_tp2_w,
-                                p->d_gwin2 + p->off2[a], st), "recon adjoint S2");
+    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gs, (int)(Dpad / 128), max_n1 / 128, nat, st), "g_S2");
+    for (int a = c0; a < c0 + nat; ++a) {
+      const int64_t i = a - c0;
+      const int W2 = p->W[a] * p->W[a];
+      const int64_t kd = roundup(W2, 32), ldf = roundup(W2, 64);
+      const float2* Ha = (const float2*)H + H_off[a];
+      // transition-potential cotangent and the position gradient through H
+      float2* gH = dL_dHconj ? (float2*)dL_dHconj + H_off[a] : gHs;
+      HIPCHK(launch_grad_h(Gm + i * bQ, R + i * bQ, Ha, n_ch, W2, (int)kd, gH, st), "g_H");
+      if (dHdx)
+        HIPCHK(launch_grad_tau(gH, (const float2*)dHdx + H_off[a], (const float2*)dHdy + H_off[a],
+                               n_ch * W2, dtau + 2 * a, st), "dtau");
+      // adjoint of the probe sum: Z[a][c][r] = sum_{u,v} exp(+2 pi i (a u/S_y + c v/S_x)) g_psi
+      HIPCHK(launch_dft_pass(gpsi + i * bGp, X, scan_sx, kd, scan_sx * kd, ldf, scan_sx * ldf, scan_sy, W2,
+                             twxc, st), "adjoint DFT x");
+      HIPCHK(launch_dft_pass(X, Z, scan_sy, scan_sx * ldf, ldf, scan_sx * ldf, ldf, scan_sx, W2, twyc, st),
+             "adjoint DFT y");
+      // reconstruction adjoints -> window cotangents
+      HIPCHK(launch_recon_adjoint(recon_args(p, a, 1), 1, Z, ldf, scan_sy, scan_sx, cb, gz, gam,
+                                  p->d_par1, p->Bp1, p->d_tp1_rp, p->d_tp1_b, p->d_tp1_w,
+                                  p->d_gwin1 + p->off1[a], st), "recon adjoint S1");
+      HIPCHK(launch_recon_adjoint(recon_args(p, a, 2), 2, gS2 + i * bGs, kd, scan_sy, scan_sx, cb, gz, gam,
+                                  p->d_par2, p->Bp2, p->d_tp2_rp, p->d_tp2_b, p->d_tp2_w,
+                                  p->d_gwin2 + p->off2[a], st), "recon adjoint S2");
+    }
   }
   // ----------------------------------------------------- reverse sweeps
   HIPCHK(launch_zero(dL_dV, G * g.nz, st), "zero dV");

@@ -18,8 +18,8 @@
 // where every 64-byte column block of the matrix is stored contiguously).  Operand chunks move from global
 // memory straight into LDS with global_load_lds_dwordx4 (no VGPR staging),
 // double buffered, one barrier per chunk; the 16-byte slots of each LDS row
-// are XOR-swizzled by (row / 4) mod 4 so that the 16 rows read by one MFMA
-// fragment load hit distinct banks.
+// are XOR-permuted (swz) so that the 16 rows read by one MFMA fragment load
+// hit distinct banks.
 //
 // Roles (epilogues):
 //   EPI_ABS2_MAP / EPI_ABS2_BEAMS
@@ -73,12 +73,36 @@ template <int PREC>
 constexpr int stage_bytes() {
   return 2 * PT<PREC>::PLANES * PLANE_TILE;
 }
+// K chunks in flight: the chunk buffers fill 128 KB of LDS (two 64 KB stages
+// for the four split planes, four 32 KB stages otherwise), so that a chunk's
+// loads have NSTAGE - 1 chunks of matrix work to land
+template <int PREC>
+constexpr int nstage() {
+  return PT<PREC>::PLANES == 4 ? 2 : 4;
+}
 template <int PREC>
 constexpr int lds_bytes() {
-  return 2 * stage_bytes<PREC>();
+  return nstage<PREC>() * stage_bytes<PREC>();
 }
 
-__device__ inline int swz(int row) { return (row >> 2) & 3; }
+// s_waitcnt vmcnt(N) lgkmcnt(0): this wave's loads older than its last N
+// have landed and its LDS reads are complete
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (0 << 8) | ((N >> 4) << 14));
+}
+
+// Workgroup barrier without the memory fence of __syncthreads, which would
+// wait for every load in flight; the waits before it are explicit (wait_vm).
+// The clobber keeps the compiler from moving memory accesses across it.
+__device__ inline void chunk_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// 16-byte slot permutation of LDS row `row`: the rows of one fragment read
+// land on distinct banks whether the LDS serves 8 lanes of 128 bytes or 16
+// lanes of 256 bytes per cycle (rows of equal parity differ in (row/4) mod 4
+// or in bit 1)
+__device__ inline int swz(int row) { return ((row >> 2) ^ (row & 2)) & 3; }
 
 template <typename T>
 __device__ inline T neg8(T a) {  // sign flip of eight 16-bit floats (bf16 or fp16)
@@ -253,6 +277,8 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
 }
 
 // acc = sum over K of A[m0 + .][k] B[n0 + .][k] (A and B point at the tile origins).
+// Chunk kc lives in LDS buffer kc mod NS; the loads of chunks kc+1 .. kc+NS-2
+// may still be in flight while chunk kc is multiplied.
 template <int PREC, bool CONJA>
 __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t lda_b, const char* B,
                                     int64_t b_plane_b, int64_t ldb_b, int K, int64_t CH, char* lds,
@@ -260,19 +286,29 @@ __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t ld
   // CH: bytes between consecutive K chunks of a row (64 when K is contiguous)
   constexpr int SB = stage_bytes<PREC>();
   constexpr int OPB = PT<PREC>::PLANES * PLANE_TILE;
+  constexpr int NS = nstage<PREC>();
+  constexpr int LPC = 4 * PT<PREC>::PLANES;  // global_load_lds per wave per chunk
   const int nk = K / PT<PREC>::BK;
-  issue_chunk<PREC>(A, a_plane_b, lda_b, 0, lds, wave, lane);
-  issue_chunk<PREC>(B, b_plane_b, ldb_b, 0, lds + OPB, wave, lane);
+  auto issue = [&](int kc) {
+    char* buf = lds + (kc % NS) * SB;
+    issue_chunk<PREC>(A, a_plane_b, lda_b, kc * CH, buf, wave, lane);
+    issue_chunk<PREC>(B, b_plane_b, ldb_b, kc * CH, buf + OPB, wave, lane);
+  };
+  for (int kc = 0; kc < NS - 1 && kc < nk; ++kc) issue(kc);
   for (int kc = 0; kc < nk; ++kc) {
-    // chunk kc has landed for every wave, and every wave is done with kc - 1
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    char* cur = lds + (kc & 1) * SB;
-    if (kc + 1 < nk) {
-      char* nxt = lds + ((kc + 1) & 1) * SB;
-      issue_chunk<PREC>(A, a_plane_b, lda_b, (kc + 1) * CH, nxt, wave, lane);
-      issue_chunk<PREC>(B, b_plane_b, ldb_b, (kc + 1) * CH, nxt + OPB, wave, lane);
+    // chunk kc has landed for every wave (the later chunks issued so far may
+    // still be in flight), and every wave is done with chunk kc - 1
+    const int later = min(NS - 2, nk - 1 - kc);
+    if constexpr (NS == 4) {
+      if (later >= 2) wait_vm<2 * LPC>();
+      else if (later == 1) wait_vm<LPC>();
+      else wait_vm<0>();
+    } else {
+      wait_vm<0>();
     }
+    chunk_barrier();
+    if (kc + NS - 1 < nk) issue(kc + NS - 1);  // into the buffer of chunk kc - 1
+    const char* cur = lds + (kc % NS) * SB;
     mma_chunk<PREC, CONJA>(cur, cur + OPB, wm, wn, lane, acc);
   }
   // all reads of the last buffer finish before the caller reuses LDS
