@@ -488,23 +488,21 @@ int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz
   int rc = slice_terms(g, n_atoms, xyz, n_terms, amp, width, terms, start, owner);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  int64_t most = 1;
-  for (int j = 0; j < g.nz; ++j) most = std::max(most, start[j + 1] - start[j]);
+  const int64_t nt_all = (int64_t)owner.size();
   double *d_terms = nullptr, *d_prof = nullptr;
+  int64_t* d_start = nullptr;
   hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)most * (g.ny + g.nx) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)std::max<int64_t>(nt_all, 1) * (g.ny + g.nx) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_start, start.size() * 8);
   if (e == hipSuccess && !terms.empty())
     e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
-  for (int j = 0; j < g.nz && e == hipSuccess; ++j) {
-    const int nt = (int)(start[j + 1] - start[j]);
-    const double* tj = d_terms + 4 * start[j];
-    float* Vj = V + (int64_t)j * g.ny * g.nx;
-    e = launch_profiles(tj, nt, g.ny, g.nx, g.ly, g.lx, 0, d_prof, nullptr, st);
-    if (e == hipSuccess) e = launch_build_slice(tj, d_prof, nt, g.ny, g.nx, Vj, st);
-  }
+  if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 0, d_prof, nullptr, st);
+  if (e == hipSuccess) e = launch_build_slices(d_terms, d_prof, d_start, g.nz, g.ny, g.nx, V, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_terms);
   (void)hipFree(d_prof);
+  (void)hipFree(d_start);
   if (e != hipSuccess) return hip_fail(e, "potential build");
   return BIP_OK;
 }
@@ -523,24 +521,24 @@ int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz,
   hipStream_t st = (hipStream_t)stream;
   int64_t most = 1;
   for (int j = 0; j < g.nz; ++j) most = std::max(most, start[j + 1] - start[j]);
-  const size_t nt_all = owner.size();
-  double *d_terms = nullptr, *d_prof = nullptr, *d_dprof = nullptr, *d_out = nullptr;
+  const int64_t nt_all = (int64_t)owner.size();
+  double *d_terms = nullptr, *d_prof = nullptr, *d_dprof = nullptr, *d_out = nullptr, *d_part = nullptr;
+  int64_t* d_start = nullptr;
+  const size_t prof_bytes = (size_t)std::max<int64_t>(nt_all, 1) * (g.ny + g.nx) * 8;
   hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)most * (g.ny + g.nx) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_dprof, (size_t)most * (g.ny + g.nx) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_out, std::max<size_t>(nt_all, 1) * 16);
+  if (e == hipSuccess) e = hipMalloc(&d_prof, prof_bytes);
+  if (e == hipSuccess) e = hipMalloc(&d_dprof, prof_bytes);
+  if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)std::max<int64_t>(nt_all, 1) * 16);
+  if (e == hipSuccess) e = hipMalloc(&d_part, (size_t)std::max<int64_t>(grad_part_doubles(nt_all, g.ny), 1) * 8);
+  if (e == hipSuccess) e = hipMalloc(&d_start, start.size() * 8);
   if (e == hipSuccess && !terms.empty())
     e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
-  for (int j = 0; j < g.nz && e == hipSuccess; ++j) {
-    const int nt = (int)(start[j + 1] - start[j]);
-    if (nt == 0) continue;
-    const double* tj = d_terms + 4 * start[j];
-    e = launch_profiles(tj, nt, g.ny, g.nx, g.ly, g.lx, 1, d_prof, d_dprof, st);
-    if (e == hipSuccess)
-      e = launch_grad_terms(tj, d_prof, d_dprof, nt, g.ny, g.nx, dL_dV + (int64_t)j * g.ny * g.nx,
-                            d_out + 2 * start[j], st);
-  }
-  std::vector<double> out(2 * nt_all);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 1, d_prof, d_dprof, st);
+  if (e == hipSuccess)
+    e = launch_grad_terms(d_terms, d_prof, d_dprof, d_start, nt_all, (int)most, g.nz, g.ny, g.nx, dL_dV,
+                          d_part, d_out, st);
+  std::vector<double> out(2 * (size_t)nt_all);
   if (e == hipSuccess && nt_all)
     e = hipMemcpyAsync(out.data(), d_out, out.size() * 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -548,9 +546,11 @@ int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz,
   (void)hipFree(d_prof);
   (void)hipFree(d_dprof);
   (void)hipFree(d_out);
+  (void)hipFree(d_part);
+  (void)hipFree(d_start);
   if (e != hipSuccess) return hip_fail(e, "potential gradient");
   for (int a = 0; a < n_atoms; ++a) dL_dxyz[3 * a] = dL_dxyz[3 * a + 1] = dL_dxyz[3 * a + 2] = 0.0;
-  for (size_t t = 0; t < nt_all; ++t) {  // terms in slice order, atoms' terms in order
+  for (int64_t t = 0; t < nt_all; ++t) {  // terms in slice order, atoms' terms in order
     dL_dxyz[3 * owner[t]] += out[2 * t];
     dL_dxyz[3 * owner[t] + 1] += out[2 * t + 1];
   }

@@ -282,14 +282,18 @@ hipError_t launch_recon_adjoint(const ReconArgs& a, int side, const float2* gsrc
                                 const int32_t* tp_b, const float* tp_w, float2* gwin,
                                 hipStream_t s);
 
-// slice potentials (k_potential.hip); terms are (x, y, A, w) quadruples of one slice
-hipError_t launch_profiles(const double* terms, int n_terms, int ny, int nx, double ly, double lx,
-                           int deriv, double* prof, double* dprof, hipStream_t s);
-hipError_t launch_build_slice(const double* terms, const double* prof, int n_terms, int ny, int nx,
-                              float* V, hipStream_t s);
+// slice potentials (k_potential.hip).  Terms are (x, y, A, w) quadruples
+// grouped by slice: slice z holds terms start[z] .. start[z + 1] (device i64).
+hipError_t launch_profiles(const double* terms, int64_t n_terms, int ny, int nx, double ly,
+                           double lx, int deriv, double* prof, double* dprof, hipStream_t s);
+hipError_t launch_build_slices(const double* terms, const double* prof, const int64_t* start, int nz,
+                               int ny, int nx, float* V, hipStream_t s);
+// partials of launch_grad_terms: grad_part_doubles(nt_all, ny) doubles
+int64_t grad_part_doubles(int64_t n_terms, int ny);
+// most: the largest term count of a slice
 hipError_t launch_grad_terms(const double* terms, const double* prof, const double* dprof,
-                             int n_terms, int ny, int nx, const float* dV, double* out,
-                             hipStream_t s);
+                             const int64_t* start, int64_t nt_all, int most, int nz, int ny, int nx,
+                             const float* dV, double* part, double* out, hipStream_t s);
 
 // contraction (k_gemm.hip)
 // grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit), (m_tiles,
