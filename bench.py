@@ -133,8 +133,9 @@ def gradient_leg(steps, warmup):
     differentiation specimen: 256^2 grid, 30 slices, 200 keV, 20 mrad, s = 4,
     16 ionized atoms x 3 channels, scan 48 x 48.  One step is the potential
     build from the positions, the forward sweeps with slice checkpoints, the
-    FP32 map, the backward (contraction, reconstruction and sweep adjoints) and
-    the position gradient reduction; host wall time around synchronized steps."""
+    map, the backward (contraction, reconstruction and sweep adjoints) and the
+    position gradient reduction, the contraction products in split precision;
+    host wall time around synchronized steps."""
     import torch
     from paper_2607_00756_amd import bip, specimen
 
@@ -156,11 +157,12 @@ def gradient_leg(steps, warmup):
     def step():
         bip.potential_build(grid, sp.xyz, amps, widths, V)
         plan.build_smatrix(V)
-        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, bip.PREC_FP32, I)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, bip.PREC_SPLIT_BF16, I)
         e = torch.cuda.Event(enable_timing=True)
         e.record()
         marks["fwd"] = e
-        plan.eels_backward(sp.n_ch, H, sp.H_off, cfg.scan, (2.0 * (I - It * I.mean())).contiguous(), dV)
+        plan.eels_backward(sp.n_ch, H, sp.H_off, cfg.scan, (2.0 * (I - It * I.mean())).contiguous(), dV,
+                           precision=bip.PREC_SPLIT_BF16)
         return bip.potential_grad(grid, sp.xyz, amps, widths, dV)
 
     for _ in range(warmup):
@@ -181,7 +183,8 @@ def gradient_leg(steps, warmup):
                         f"{cfg.alpha*1e3:.0f} mrad, s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
                         f"scan {cfg.scan[0]}x{cfg.scan[1]}, {len(sp.xyz)} atoms in the potential",
             "ms_per_gradient": ms, "ms_forward": fwd_ms / steps, "ms_backward": ms - fwd_ms / steps,
-            "steps": steps, "outputs": "dL/dV [nz, ny, nx] and dL/dxyz of every atom (FP32 map, FP64 reductions)"}
+            "steps": steps, "precision": "split (FP16 Gram, hi+lo BF16 products)",
+            "outputs": "dL/dV [nz, ny, nx] and dL/dxyz of every atom (FP64 potential reductions)"}
 
 
 def measured_traffic(stage):

@@ -167,9 +167,13 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
  * Requires a plan created with ckpt_stride = 1 and a bip_build_smatrix of the
  * same V: the reverse sweeps read the slice checkpoints it kept.  All atoms
  * of the plan contribute; the map is the one bip_eels_signal returns for
- * out_mode BIP_OUT_MAP with the same H and raster.  The contraction is
- * recomputed in FP32 whatever precision the forward map used.
+ * out_mode BIP_OUT_MAP with the same H and raster.  The contraction and its
+ * adjoint products are recomputed atom by atom (batched over chunks of atoms)
+ * in `precision`.
  *   H, H_off, n_ch, scan_sy/sx   as for bip_eels_signal.
+ *   precision  BIP_PREC_FP32 or BIP_PREC_SPLIT_BF16 (the products of the
+ *              forward's split precision: FP16 Gram matrix, hi+lo BF16 for
+ *              the rest); other values give BIP_EINVAL.
  *   dL_dI      device f32 [P]: dL/dI(rho) of the loss L(I) (e.g. 2 (I - I_t)).
  *   dL_dV      device f32 [nz][ny][nx], overwritten: dL/dV_j(r).
  *   dL_dHconj  device complex64, ragged like H, or NULL: the Wirtinger
@@ -185,7 +189,8 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
  * BIP_EUNSUPPORTED (raster sides above 256), BIP_ENOMEM, BIP_EHIP.
  */
 int bip_eels_backward(bip_plan* plan, int32_t n_ch, const float* H, const int64_t* H_off,
-                      int32_t scan_sy, int32_t scan_sx, const float* dL_dI, float* dL_dV,
+                      int32_t scan_sy, int32_t scan_sx, int32_t precision, const float* dL_dI,
+                      float* dL_dV,
                       float* dL_dHconj, const float* dHdx, const float* dHdy, double* dL_dtau_xy,
                       void* stream);
 

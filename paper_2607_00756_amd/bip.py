@@ -56,8 +56,8 @@ _lib.bip_parent_windows.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p]
 _lib.bip_query.argtypes = [_p, ctypes.c_int32, _p]
 _lib.bip_set_profiling.argtypes = [_p, ctypes.c_int32]
 _lib.bip_stage_timings.argtypes = [_p, _p, _p, ctypes.c_int32]
-_lib.bip_eels_backward.argtypes = [_p, ctypes.c_int32, _p, _p, ctypes.c_int32, ctypes.c_int32, _p,
-                                   _p, _p, _p, _p, _p, _p]
+_lib.bip_eels_backward.argtypes = [_p, ctypes.c_int32, _p, _p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, _p, _p, _p, _p, _p, _p, _p]
 _lib.bip_potential_build.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
                                      _p, _p, _p, _p]
 _lib.bip_potential_grad.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
@@ -158,15 +158,17 @@ class Plan:
                                     _stream(stream)))
 
     def eels_backward(self, n_ch, H, H_off, scan, dL_dI, dL_dV, dL_dHconj=None, dHdx=None,
-                      dHdy=None, want_tau=False, stream=None):
+                      dHdy=None, want_tau=False, precision=PREC_FP32, stream=None):
         """Gradient of a map loss (plan made with ckpt_stride=1, after build_smatrix).
         dL_dI: float32 device [P]; dL_dV: float32 device [nz, ny, nx] (written);
-        dL_dHconj / dHdx / dHdy: complex64 device, ragged like H, or None.
+        dL_dHconj / dHdx / dHdy: complex64 device, ragged like H, or None;
+        precision: PREC_FP32 or PREC_SPLIT_BF16 for the contraction products.
         Returns dL/dtau_xy [n_atoms, 2] (float64) when want_tau, else None."""
         offs, op = _host(H_off, np.int64)
         tau = np.zeros((self.n_atoms, 2), np.float64) if want_tau else None
         _check(_lib.bip_eels_backward(self._h, int(n_ch), _ptr(H), op, int(scan[0]), int(scan[1]),
-                                      _ptr(dL_dI), _ptr(dL_dV), _ptr(dL_dHconj), _ptr(dHdx),
+                                      int(precision), _ptr(dL_dI), _ptr(dL_dV), _ptr(dL_dHconj),
+                                      _ptr(dHdx),
                                       _ptr(dHdy),
                                       tau.ctypes.data_as(ctypes.c_void_p) if want_tau else None,
                                       _stream(stream)))
@@ -243,6 +245,7 @@ class EELSMap(torch.autograd.Function):
         plan.build_smatrix(V.contiguous())
         plan.eels_signal(n_ch, H.contiguous(), H_off, scan, OUT_MAP, precision, out)
         ctx.plan, ctx.n_ch, ctx.H_off, ctx.scan = plan, n_ch, H_off, scan
+        ctx.precision = PREC_FP32 if precision == PREC_FP32 else PREC_SPLIT_BF16
         ctx.save_for_backward(V, H)
         return out
 
@@ -254,7 +257,8 @@ class EELSMap(torch.autograd.Function):
         # the checkpoints belong to the last build: rebuild if another V was built since
         ctx.plan.build_smatrix(V.contiguous())
         ctx.plan.eels_backward(ctx.n_ch, H.contiguous(), ctx.H_off, ctx.scan,
-                               grad_I.contiguous().float(), dV, dL_dHconj=gH)
+                               grad_I.contiguous().float(), dV, dL_dHconj=gH,
+                               precision=ctx.precision)
         return dV, (2.0 * gH if gH is not None else None), None, None, None, None, None
 
 

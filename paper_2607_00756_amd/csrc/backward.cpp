@@ -49,7 +49,8 @@ using namespace bip;
 extern "C" {
 
 int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
-                      int32_t scan_sy, int32_t scan_sx, const float* dL_dI, float* dL_dV,
+                      int32_t scan_sy, int32_t scan_sx, int32_t precision, const float* dL_dI,
+                      float* dL_dV,
                       float* dL_dHconj, const float* dHdx, const float* dHdy, double* dL_dtau_xy,
                       void* stream) {
   if (!p || !H || !H_off || !dL_dI || !dL_dV) return err(BIP_EINVAL, "NULL argument");
@@ -59,6 +60,8 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
   if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)
     return err(BIP_EUNSUPPORTED, "scan raster sides above " + std::to_string(BIP_MAX_SCAN));
+  if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16)
+    return err(BIP_EINVAL, "backward precision must be BIP_PREC_FP32 or BIP_PREC_SPLIT_BF16");
   if ((dHdx == nullptr) != (dHdy == nullptr)) return err(BIP_EINVAL, "dHdx and dHdy go together");
   if (dL_dtau_xy && !dHdx) return err(BIP_EINVAL, "dL_dtau_xy needs dHdx and dHdy");
   for (int a = 0; a < p->n_atoms; ++a)
@@ -70,7 +73,13 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   const int P = scan_sy * scan_sx;
   const int64_t Ppad = roundup(P, 128);
   const int64_t Dpad = roundup(p->ndet, 128), Dk = roundup(p->ndet, 32);
-  const int BKF = gemm_bk(BIP_PREC_FP32);
+  // operand precisions: as the forward's map (the Gram matrix on FP16 products
+  // of a 2^8-scaled operand in split precision)
+  const int prec = precision;
+  const int gprec = prec == BIP_PREC_SPLIT_BF16 ? BIP_PREC_FP16 : BIP_PREC_FP32;
+  const float gsc = gprec == BIP_PREC_FP16 ? 256.f : 1.f;
+  const int64_t esz = prec == BIP_PREC_FP32 ? 4 : 2, gesz = gprec == BIP_PREC_FP32 ? 4 : 2;
+  const int BKF = gemm_bk(gprec);
   int Wmax = 0;
   for (int a = 0; a < p->n_atoms; ++a) Wmax = std::max(Wmax, p->W[a]);
   const int64_t W2m = (int64_t)Wmax * Wmax, kdm = roundup(W2m, 32), n1m = roundup(W2m, 128),
@@ -178,15 +187,17 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   GemmJob* d_jobs = (GemmJob*)ws.take(4 * (size_t)p->n_atoms * sizeof(GemmJob));
   const int64_t NA = nat_max;
   float2* X = (float2*)ws.take((size_t)(NA * bX) * 8);
-  float* psiT = (float*)ws.take((size_t)(2 * NA * bPsi) * 4);
-  float* S2b = (float*)ws.take((size_t)(2 * NA * bS2b) * 4);
-  float* S2d = (float*)ws.take((size_t)(2 * NA * bS2d) * 4);
-  float* Qp = (float*)ws.take((size_t)(2 * NA * bQ) * 4);
+  // operand planes: 8 bytes per element in FP32 (two planes) and in split
+  // precision (four 2-byte planes); plane strides below are in elements
+  char* psiT = (char*)ws.take((size_t)(2 * NA * bPsi) * 4);
+  char* S2b = (char*)ws.take((size_t)(2 * NA * bS2b) * 4);
+  char* S2d = (char*)ws.take((size_t)(2 * NA * bS2d) * 4);
+  char* Qp = (char*)ws.take((size_t)(2 * NA * bQ) * 4);
   float2* Gm = (float2*)ws.take((size_t)(NA * bQ) * 8);
-  float* A1 = (float*)ws.take((size_t)(2 * NA * bA) * 4);
-  float* B1 = (float*)ws.take((size_t)(2 * NA * bA) * 4);
+  char* A1 = (char*)ws.take((size_t)(2 * NA * bA) * 4);
+  char* B1 = (char*)ws.take((size_t)(2 * NA * bA) * 4);
   float2* R = (float2*)ws.take((size_t)(NA * bQ) * 8);
-  float* Kp = (float*)ws.take((size_t)(2 * NA * bQ) * 4);
+  char* Kp = (char*)ws.take((size_t)(2 * NA * bQ) * 4);
   float2* gpsi = (float2*)ws.take((size_t)(NA * bGp) * 8);
   float2* gS2 = (float2*)ws.take((size_t)(NA * bGs) * 8);
   if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: backward workspace");
@@ -290,19 +301,22 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     // psi^T [rho][r] (FP32) of every atom of the chunk, exactly as the forward synthesis
     pa.jobs = d_probe + c0;
     HIPCHK(launch_probe_fold_x(pa, max_w2, nat, st), "probe fold");
-    HIPCHK(launch_probe_y(pa, BIP_PREC_FP32, false, max_kd, nat, st), "probe synthesis");
+    HIPCHK(launch_probe_y(pa, prec, false, max_kd, nat, st), "probe synthesis");
     for (int a = c0; a < c0 + nat; ++a) {
       const int64_t i = a - c0;
       const int W2 = p->W[a] * p->W[a];
       const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
-      // S2~ K-blocked (Gram) and [d][r] (gradient product), FP32
-      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2b + i * bS2b, 0, BIP_PREC_FP32, Dk, n1, Dk,
-                                  NA * bS2b, st), "recon S2");
-      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2d + i * bS2d, 1, BIP_PREC_FP32, kd, Dpad, kd,
+      // S2~ K-blocked (Gram) and [d][r] (gradient product)
+      ReconArgs ra = recon_args(p, a, 2);
+      ra.scale = gsc;
+      HIPCHK(launch_recon_operand(ra, S2b + i * bS2b * gesz, 0, gprec, Dk, n1, Dk, NA * bS2b, st),
+             "recon S2");
+      HIPCHK(launch_recon_operand(recon_args(p, a, 2), S2d + i * bS2d * esz, 1, prec, kd, Dpad, kd,
                                   NA * bS2d, st), "recon S2");
       // conj(psi) and Ibar psi as [r][rho] operands of R
-      HIPCHK(launch_psi_transpose(psiT + i * bPsi, NA * bPsi, (int)kd, W2, P, (int)Ppad, (int)n1, ibar,
-                                  A1 + i * bA, B1 + i * bA, NA * bA, st), "psi transpose");
+      HIPCHK(launch_psi_transpose(prec, psiT + i * bPsi * esz, NA * bPsi, (int)kd, W2, P, (int)Ppad,
+                                  (int)n1, ibar, A1 + i * bA * esz, B1 + i * bA * esz, NA * bA, st),
+             "psi transpose");
     }
     // Gram matrix G and Q = G o Hc
     GemmArgs ga{};
@@ -316,8 +330,8 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     ga.out_plane = NA * bQ;
     ga.out2 = Gm;
     ga.tiles = max_n1 / 128;
-    ga.gscale = 1.f;
-    HIPCHK(launch_zgemm_gram(BIP_PREC_FP32, BIP_PREC_FP32, ga, (int)gemm_gram_blocks(ga.tiles, nat), st), "Gram");
+    ga.gscale = 1.f / (gsc * gsc);
+    HIPCHK(launch_zgemm_gram(gprec, prec, ga, (int)gemm_gram_blocks(ga.tiles, nat), st), "Gram");
     // R = conj(psi) diag(Ibar) psi^T over the raster
     GemmArgs gr{};
     gr.A = A1;
@@ -327,13 +341,13 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     gr.njobs = nat;
     gr.out = R;
     gr.m_store = max_n1;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE + EPI_CONJ_A, gr, max_n1 / 128, max_n1 / 128, nat, st), "R");
+    HIPCHK(launch_zgemm(prec, EPI_STORE + EPI_CONJ_A, gr, max_n1 / 128, max_n1 / 128, nat, st), "R");
     for (int a = c0; a < c0 + nat; ++a) {
       const int64_t i = a - c0;
       const int W2 = p->W[a] * p->W[a];
       const int64_t kd = roundup(W2, 32), n1 = roundup(W2, 128);
-      HIPCHK(launch_kmat(R + i * bQ, (const float2*)H + H_off[a], n_ch, W2, (int)kd, (int)n1, Kp + i * bQ,
-                         NA * bQ, st), "K");
+      HIPCHK(launch_kmat(prec, R + i * bQ, (const float2*)H + H_off[a], n_ch, W2, (int)kd, (int)n1,
+                         Kp + i * bQ * esz, NA * bQ, st), "K");
     }
     // g_psi = Ibar (Q psi) and g_S2~ = S2~ K^T
     GemmArgs gp{};
@@ -346,7 +360,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     gp.out = gpsi;
     gp.rowscale = ibar;
     gp.m_store = (int)Ppad;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gp, (int)(Ppad / 128), max_n1 / 128, nat, st), "g_psi");
+    HIPCHK(launch_zgemm(prec, EPI_STORE, gp, (int)(Ppad / 128), max_n1 / 128, nat, st), "g_psi");
     GemmArgs gs{};
     gs.A = S2d;
     gs.a_plane = NA * bS2d;
@@ -356,7 +370,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     gs.njobs = nat;
     gs.out = gS2;
     gs.m_store = (int)Dpad;
-    HIPCHK(launch_zgemm(BIP_PREC_FP32, EPI_STORE, gs, (int)(Dpad / 128), max_n1 / 128, nat, st), "g_S2");
+    HIPCHK(launch_zgemm(prec, EPI_STORE, gs, (int)(Dpad / 128), max_n1 / 128, nat, st), "g_S2");
     for (int a = c0; a < c0 + nat; ++a) {
       const int64_t i = a - c0;
       const int W2 = p->W[a] * p->W[a];

@@ -267,11 +267,12 @@ hipError_t launch_dft_pass(const float2* in, float2* out, int S, int64_t js, int
                            int64_t os2, int n_outer, int W2, const float2* tws, hipStream_t s);
 
 // gradient kernels (k_backward.hip)
-hipError_t launch_psi_transpose(const float* psiT, int64_t psp, int kd, int W2, int P, int Ppad,
-                                int n1, const float* ibar, float* A1, float* B1, int64_t apl,
+// prec: BIP_PREC_FP32 or BIP_PREC_SPLIT_BF16 (operand planes)
+hipError_t launch_psi_transpose(int prec, const void* psiT, int64_t psp, int kd, int W2, int P,
+                                int Ppad, int n1, const float* ibar, void* A1, void* B1, int64_t apl,
                                 hipStream_t s);
-hipError_t launch_kmat(const float2* R, const float2* H, int n_ch, int W2, int kd, int n1, float* Kp,
-                       int64_t kpl, hipStream_t s);
+hipError_t launch_kmat(int prec, const float2* R, const float2* H, int n_ch, int W2, int kd, int n1,
+                       void* Kp, int64_t kpl, hipStream_t s);
 hipError_t launch_grad_h(const float2* G, const float2* R, const float2* H, int n_ch, int W2, int kd,
                          float2* gH, hipStream_t s);
 hipError_t launch_grad_tau(const float2* gH, const float2* dHx, const float2* dHy, int n,

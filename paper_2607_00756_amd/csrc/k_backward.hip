@@ -15,16 +15,19 @@
 //   g_D_p = sum_b w_bp (g_z,b + gamma_b D_p/|D_p|);
 // the cotangent of the parent column is conj(de-tilt carrier) g_D_p.
 #include "bip_internal.h"
+#include "planes.h"
 #include "recon_core.h"
 
 namespace bip {
 
 namespace {
 
-// A1[r][rho] = psi(r, rho), B1[r][rho] = Ibar(rho) psi(r, rho) (FP32 planes,
-// rows up to n1, columns up to Ppad) from psi^T [rho][r] (FP32 planes).
-__global__ void k_psi_transpose(const float* __restrict__ psiT, int64_t psp, int kd, int W2, int P,
-                                int Ppad, const float* __restrict__ ibar, float* A1, float* B1,
+// A1[r][rho] = psi(r, rho), B1[r][rho] = Ibar(rho) psi(r, rho) (operand planes
+// of precision PREC, rows up to n1, columns up to Ppad) from psi^T [rho][r]
+// (planes of the same precision).
+template <int PREC>
+__global__ void k_psi_transpose(const void* __restrict__ psiT, int64_t psp, int kd, int W2, int P,
+                                int Ppad, const float* __restrict__ ibar, void* A1, void* B1,
                                 int64_t apl) {
   __shared__ float2 tile[32][33];
   const int rho0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
@@ -32,7 +35,7 @@ __global__ void k_psi_transpose(const float* __restrict__ psiT, int64_t psp, int
   for (int k = 0; k < 32; k += 8) {
     const int rho = rho0 + ty + k, r = r0 + tx;
     float2 v = make_float2(0.f, 0.f);
-    if (rho < P && r < W2) v = make_float2(psiT[(int64_t)rho * kd + r], psiT[psp + (int64_t)rho * kd + r]);
+    if (rho < P && r < W2) v = load_planes<PREC>(psiT, (int64_t)rho * kd + r, psp);
     tile[ty + k][tx] = v;
   }
   __syncthreads();
@@ -41,17 +44,16 @@ __global__ void k_psi_transpose(const float* __restrict__ psiT, int64_t psp, int
     const float2 v = tile[tx][ty + k];
     const float s = rho < P ? ibar[rho] : 0.f;
     const int64_t i = (int64_t)r * Ppad + rho;
-    A1[i] = v.x;
-    A1[i + apl] = v.y;
-    B1[i] = s * v.x;
-    B1[i + apl] = s * v.y;
+    store_planes<PREC>(A1, i, apl, v.x, v.y);
+    store_planes<PREC>(B1, i, apl, s * v.x, s * v.y);
   }
 }
 
-// K[r][r'] = R[r][r'] sum_n conj(H_n(r)) H_n(r') as FP32 planes (zero outside
-// the window), rows up to n1, columns up to kd.
+// K[r][r'] = R[r][r'] sum_n conj(H_n(r)) H_n(r') as operand planes of
+// precision PREC (zero outside the window), rows up to n1, columns up to kd.
+template <int PREC>
 __global__ void k_kmat(const float2* __restrict__ R, const float2* __restrict__ H, int n_ch, int W2,
-                       int kd, int n1, float* Kp, int64_t kpl) {
+                       int kd, int n1, void* Kp, int64_t kpl) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n1 * kd) return;
   const int r = (int)(i / kd), c = (int)(i - (int64_t)r * kd);
@@ -67,8 +69,7 @@ __global__ void k_kmat(const float2* __restrict__ R, const float2* __restrict__ 
     kr = q.x * hr - q.y * hi;
     ki = q.x * hi + q.y * hr;
   }
-  Kp[i] = kr;
-  Kp[i + kpl] = ki;
+  store_planes<PREC>(Kp, i, kpl, kr, ki);
 }
 
 // Fixed-order reduction of a float2 over a 256-thread block.
@@ -222,19 +223,31 @@ __global__ __launch_bounds__(256) void k_recon_adj_b(ReconArgs a, const int2* __
 
 }  // namespace
 
-hipError_t launch_psi_transpose(const float* psiT, int64_t psp, int kd, int W2, int P, int Ppad,
-                                int n1, const float* ibar, float* A1, float* B1, int64_t apl,
+hipError_t launch_psi_transpose(int prec, const void* psiT, int64_t psp, int kd, int W2, int P,
+                                int Ppad, int n1, const float* ibar, void* A1, void* B1, int64_t apl,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_psi_transpose, dim3(Ppad / 32, n1 / 32), dim3(256), 0, s, psiT, psp, kd, W2,
-                     P, Ppad, ibar, A1, B1, apl);
+  const dim3 grid(Ppad / 32, n1 / 32);
+  if (prec == BIP_PREC_FP32)
+    hipLaunchKernelGGL(k_psi_transpose<BIP_PREC_FP32>, grid, dim3(256), 0, s, psiT, psp, kd, W2, P,
+                       Ppad, ibar, A1, B1, apl);
+  else if (prec == BIP_PREC_SPLIT_BF16)
+    hipLaunchKernelGGL(k_psi_transpose<BIP_PREC_SPLIT_BF16>, grid, dim3(256), 0, s, psiT, psp, kd, W2,
+                       P, Ppad, ibar, A1, B1, apl);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_kmat(const float2* R, const float2* H, int n_ch, int W2, int kd, int n1, float* Kp,
-                       int64_t kpl, hipStream_t s) {
+hipError_t launch_kmat(int prec, const float2* R, const float2* H, int n_ch, int W2, int kd, int n1,
+                       void* Kp, int64_t kpl, hipStream_t s) {
   const int64_t n = (int64_t)n1 * kd;
-  hipLaunchKernelGGL(k_kmat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R, H, n_ch, W2, kd,
-                     n1, Kp, kpl);
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (prec == BIP_PREC_FP32)
+    hipLaunchKernelGGL(k_kmat<BIP_PREC_FP32>, grid, dim3(256), 0, s, R, H, n_ch, W2, kd, n1, Kp, kpl);
+  else if (prec == BIP_PREC_SPLIT_BF16)
+    hipLaunchKernelGGL(k_kmat<BIP_PREC_SPLIT_BF16>, grid, dim3(256), 0, s, R, H, n_ch, W2, kd, n1, Kp, kpl);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

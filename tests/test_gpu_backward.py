@@ -35,7 +35,7 @@ def _ragged(s):
     return cfg, tp
 
 
-def _gpu_grad(cfg, tp, ibar, recon, dHx=None, dHy=None, batch=None):
+def _gpu_grad(cfg, tp, ibar, recon, dHx=None, dHy=None, batch=None, prec=0):
     torch, dev = torch_dev()
     bip = _bip()
     if batch is not None:
@@ -56,16 +56,18 @@ def _gpu_grad(cfg, tp, ibar, recon, dHx=None, dHy=None, batch=None):
         dy = torch.from_numpy(np.ascontiguousarray(dHy, np.complex64)).to(dev)
     Ib = torch.from_numpy(np.ascontiguousarray(ibar, np.float32)).to(dev)
     tau = plan.eels_backward(tp.n_ch, H, tp.H_off, cfg.scan, Ib, dV, dL_dHconj=gH, dHdx=dx,
-                             dHdy=dy, want_tau=dHx is not None)
+                             dHdy=dy, want_tau=dHx is not None, precision=prec)
     torch.cuda.synchronize()
     out = dV.cpu().numpy().astype(np.float64), gH.cpu().numpy().astype(np.complex128), tau
     plan.close()
     return out
 
 
-@pytest.mark.parametrize("s,recon,batch", [(2, E.RECON_MAGNITUDE, None), (1, E.RECON_MAGNITUDE, None),
-                                           (2, E.RECON_COMPLEX, None), (3, E.RECON_MAGNITUDE, 7)])
-def test_backward_matches_oracle_gradient(s, recon, batch):
+@pytest.mark.parametrize("s,recon,batch,prec", [(2, E.RECON_MAGNITUDE, None, 0), (1, E.RECON_MAGNITUDE, None, 0),
+                                                (2, E.RECON_COMPLEX, None, 0), (3, E.RECON_MAGNITUDE, 7, 0),
+                                                (2, E.RECON_MAGNITUDE, None, 1), (3, E.RECON_COMPLEX, 7, 1)])
+def test_backward_matches_oracle_gradient(s, recon, batch, prec):
+    """prec 0: FP32 products; 1: the split precision (FP16 Gram, hi+lo BF16)."""
     cfg, tp = _ragged(s)
     prob = as_oracle_problem(tp)
     r = np.random.default_rng(4)
@@ -76,10 +78,10 @@ def test_backward_matches_oracle_gradient(s, recon, batch):
     dH = {a: (dHx[tp.H_off[a]:tp.H_off[a + 1]].reshape(tp.n_ch, tp.win_size[a], tp.win_size[a]),
               dHy[tp.H_off[a]:tp.H_off[a + 1]].reshape(tp.n_ch, tp.win_size[a], tp.win_size[a]))
           for a in range(len(tp.tau))}
-    print(f"[backward s={s} recon={recon} batch={batch}]", flush=True)
+    print(f"[backward s={s} recon={recon} batch={batch} prec={prec}]", flush=True)
     ref = A.MapGradient(prob, recon).run(It, dH_dtau=dH)
     ibar = 2.0 * (ref["I"] - It)
-    dV, gH, tau = _gpu_grad(cfg, tp, ibar, recon, dHx, dHy, batch)
+    dV, gH, tau = _gpu_grad(cfg, tp, ibar, recon, dHx, dHy, batch, prec)
     e_v = rel_l2(dV, ref["dV"])
     gH_ref = np.concatenate([ref["gH"][a].ravel() for a in range(len(tp.tau))])
     e_h = float(np.linalg.norm(gH - gH_ref) / np.linalg.norm(gH_ref))
