@@ -565,6 +565,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   ProbeJob* d_probe = (ProbeJob*)ws.take(atoms.size() * sizeof(ProbeJob));
   int32_t* d_cells = (int32_t*)ws.take(cells.size() * 4);
   float2* d_tws = (float2*)ws.take(tws.size() * 8);
+  ReconAtom* d_ratoms = (ReconAtom*)ws.take(atoms.size() * sizeof(ReconAtom));
   const size_t chunk_base = ws.used;
   if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: tables exceed the workspace");
   HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
@@ -646,6 +647,18 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       }
     }
   }
+  // batched S2~ operand reconstruction of the Gram path (square-lattice parents)
+  const bool recon_batched = gram && p->tile_np2 <= TILE_NP;
+  std::vector<ReconAtom>& ratoms = p->h_ratoms;
+  ratoms.clear();
+  if (recon_batched) {
+    for (size_t i = 0; i < atoms.size(); ++i) {
+      const int a = atoms[i];
+      ratoms.push_back(ReconAtom{p->off2[a], off[1][i], p->W[a], p->oy[a], p->ox[a], (int32_t)n1_of(p->W[a])});
+    }
+    HIPCHK(hipMemcpyAsync(d_ratoms, ratoms.data(), ratoms.size() * sizeof(ReconAtom), hipMemcpyHostToDevice, st),
+           "recon atoms");
+  }
   GemmJob* d_jdet = d_jobs;
   GemmJob* d_jquad = d_jdet + jdet.size();
   HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
@@ -698,7 +711,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
           off[3][i] + s[3] > pl3)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-      if (gram) {
+      if (gram && !recon_batched) {
         ReconArgs ra = recon_args(p, a, 2);
         ra.scale = gram_scale;
         HIPCHK(timed(p, ST_RECON, st, [&] {
@@ -706,12 +719,21 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
                                              pl1, st);
                }),
                "recon S2 operand");
-      } else
+      } else if (!gram)
         HIPCHK(timed(p, ST_RECON, st, [&] {
                  return launch_recon_operand(recon_args(p, a, 2), S2op + off[1][i] * esz, 1, precision,
                                              kd_of(W), Dpad, kd_of(W), pl1, st);
                }),
                "recon S2 operand");
+    }
+    if (recon_batched) {
+      ReconArgs ra = recon_args(p, atoms[c0], 2);
+      ra.win = p->d_win2;
+      ra.scale = gram_scale;
+      HIPCHK(timed(p, ST_RECON, st, [&] {
+               return launch_recon_kblk_atoms(ra, d_ratoms + c0, nat, S2op, gram_prec, Dk, pl1, st);
+             }),
+             "recon S2 operand");
     }
     // probe synthesis for every atom of the chunk (grid z = atom)
     pa.jobs = d_probe + c0;

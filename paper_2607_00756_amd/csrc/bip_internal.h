@@ -50,6 +50,14 @@ struct GemmJob {
                          // B (0: contiguous; K-blocked operands: row count x chunk width)
 };
 
+// One atom of a batched K-blocked operand reconstruction.
+struct ReconAtom {
+  int64_t win_off;  // the atom's parent windows in the window stack (complex elements)
+  int64_t out_off;  // the atom's operand block (plane elements)
+  int32_t W, oy, ox;
+  int32_t n_r;      // operand rows (window pixels rounded up to whole tiles)
+};
+
 enum Epilogue { EPI_ABS2_MAP = 0, EPI_ABS2_BEAMS, EPI_GRAMQ, EPI_QUAD, EPI_STORE };
 
 struct GemmArgs {
@@ -165,6 +173,7 @@ struct bip_plan {
   size_t work_bytes = 0;
   // host tables read by asynchronous copies; kept alive until the next call
   std::vector<bip::GemmJob> h_jobs2, h_jobs3;
+  std::vector<bip::ReconAtom> h_ratoms;
   std::vector<int32_t> h_qstart, h_qlist;
   std::vector<bip::ProbeJob> h_probe;
   std::vector<int32_t> h_cells;   // cell_start then cell_beams
@@ -249,6 +258,11 @@ struct ReconArgs {
 };
 // plain complex64 output [nb][W*W]
 hipError_t launch_recon_plain(const ReconArgs& a, float2* out, hipStream_t s);
+// K-blocked operands (kind 0) of n_atoms atoms in one launch; a.win is the
+// window stack, the per-atom fields of a are taken from atoms (device).
+// Needs a.tile_np <= 64 (square-lattice parents).
+hipError_t launch_recon_kblk_atoms(const ReconArgs& a, const ReconAtom* atoms, int n_atoms, void* out,
+                                   int prec, int64_t ncols_pad, int64_t plane_stride, hipStream_t s);
 // GEMM operand outputs; layout kind 0: [r][b] (b fastest, ld = ldk, rows up to nrows)
 // kind 1: [b][r] (r fastest).  prec: BIP_PREC_*; planes at stride plane_stride elements.
 hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int prec, int64_t ld,

@@ -231,22 +231,16 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
 // offsets and the stores of a wave cover 64 consecutive beams of one row.
 constexpr int KR = 33;  // padded LDS row of the slab
 
+// One beam tile bt of one atom over pixel tiles rt_lo .. rt_hi - 1 (a holds
+// the atom's window; out its operand block).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int nrows, int ncols,
-                                                    int64_t plane, int rpw) {
+__device__ inline void recon_kblk_tile(const ReconArgs& a, void* out, int n_r, int n_b, int64_t plane,
+                                       int bt, int rt_lo, int rt_hi) {
   __shared__ float2 sP[TILE_NP][KR];
   __shared__ float sM[TILE_NP][KR];
   extern __shared__ float2 s_tw[];  // exp(-2 pi i k/L), L entries
   constexpr int NPF = TILE_NP * TR / 256;
   constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
-  const int n_b = ncols, n_r = nrows;
-  const int nbt = (n_b + TB - 1) / TB, nrt = (n_r + TR - 1) / TR;
-  const int nch = (nrt + rpw - 1) / rpw;
-  const int per = (int)(gridDim.x / 8);
-  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (lin >= nbt * nch) return;
-  const int bt = lin % nbt, ch = lin / nbt;
-  const int rt_lo = ch * rpw, rt_hi = min(nrt, rt_lo + rpw);
   const int b0 = bt * TB;
   const int W2 = a.W * a.W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -274,20 +268,20 @@ __global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int 
   ec[7] = bvalid ? a.ellc[(int64_t)b * ELL_W + 7] : 0;
   const int2 h = bvalid ? a.beams[b] : make_int2(0, 0);
   const int ky = h.x * (a.L / a.ny), kx = h.y * (a.L / a.nx);
-  // slab rows: element i = (parent i / TR, pixel i % TR)
-  int prow[NPF];
+  // slab rows: element i = (parent i / TR, pixel i % TR); each thread reads
+  // pixel threadIdx.x % TR of parents threadIdx.x / TR + 8q (row pointers kept)
+  const float2* prow[NPF];
 #pragma unroll
   for (int q = 0; q < NPF; ++q) {
     const int i = threadIdx.x + 256 * q;
-    prow[q] = i < n_t * TR ? a.tpar[ts + i / TR] : -1;
+    prow[q] = i < n_t * TR ? a.win + (int64_t)a.tpar[ts + i / TR] * W2 + (threadIdx.x % TR) : nullptr;
   }
   float2 pre[NPF];
   auto load_slab = [&](int rt) {
+    const int r = rt * TR + (int)(threadIdx.x % TR);
 #pragma unroll
-    for (int q = 0; q < NPF; ++q) {
-      const int r = rt * TR + ((threadIdx.x + 256 * q) % TR);
-      pre[q] = (prow[q] >= 0 && r < W2) ? a.win[(int64_t)prow[q] * W2 + r] : make_float2(0.f, 0.f);
-    }
+    for (int q = 0; q < NPF; ++q)
+      pre[q] = (prow[q] && r < W2) ? prow[q][rt * TR] : make_float2(0.f, 0.f);
   };
   auto store_slab = [&]() {
 #pragma unroll
@@ -307,28 +301,58 @@ __global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int 
   const char* sMb = (const char*)&sM[0][0];
   const int64_t ob = (int64_t)(b / KB) * n_r * KB + b % KB;  // this lane's column of the blocks
   const bool bstore = b < n_b;
+  // Lanes of padded beams have zero weights, so their outputs come out zero
+  // without a select; pixels beyond the window and tiles of padded beams only
+  // (no slab) store zeros.  The CSR tail is taken only by waves that hold a
+  // row longer than six.
+  const bool live = b0 < a.nb;
+  const bool wave_tail = __ballot(ec[6] > ELL_K) != 0;
+  const bool mag = a.mode == BIP_RECON_MAGNITUDE;
+  const float sc = a.retilt_sign > 0 ? -a.scale : a.scale;  // conj(t) = (t.x, -t.y) via the sign
+  constexpr int ES = PREC == BIP_PREC_FP32 ? 4 : 2;  // bytes per plane element
   for (int rt = rt_lo; rt < rt_hi; ++rt) {
+    // this lane's output column at the wave's first pixel: the pixel loop
+    // below stores at immediate offsets from it
+    char* obase = (char*)out + (ob + (int64_t)(rt * TR + 8 * wave) * KB) * ES;
 #pragma unroll
     for (int i = 0; i < TR / 4; ++i) {
       const int r = rt * TR + 8 * wave + i;  // window pixel (wave-uniform)
-      const int ry = r / a.W, rx = r - ry * a.W;
-      const int py = (a.oy + ry) & (a.ny - 1), px = (a.ox + rx) & (a.nx - 1);
-      float2 z = make_float2(0.f, 0.f);
-      float m = 0.f;
+      if (r >= n_r) break;
+      float2 v = make_float2(0.f, 0.f);
+      if (live && r < W2) {
+        const int ry = r / a.W, rx = r - ry * a.W;
+        const int py = (a.oy + ry) & (a.ny - 1), px = (a.ox + rx) & (a.nx - 1);
+        float2 z = make_float2(0.f, 0.f);
+        float m = 0.f;
 #pragma unroll
-      for (int j = 0; j < ELL_K; ++j) {
-        const float2 d = *(const float2*)(sPb + oP[j] + i * (int)sizeof(float2));
-        const float dm = *(const float*)(sMb + oM[j] + i * (int)sizeof(float));
-        z.x += wt[j] * d.x;
-        z.y += wt[j] * d.y;
-        m += wt[j] * dm;
+        for (int j = 0; j < ELL_K; ++j) {
+          const float2 d = *(const float2*)(sPb + oP[j] + i * (int)sizeof(float2));
+          const float dm = *(const float*)(sMb + oM[j] + i * (int)sizeof(float));
+          z.x += wt[j] * d.x;
+          z.y += wt[j] * d.y;
+          m += wt[j] * dm;
+        }
+        if (wave_tail) recon_tail(z, m, a.win, W2, r, ec, a.col, a.w);
+        if (mag) {
+          // m z/|z| with the hardware reciprocal square root (0 where z = 0,
+          // e.g. padded beams); 0 < |z|^2 < 1e-30 (no such lane in practice)
+          // takes mag_rescale's exact path
+          const float q = z.x * z.x + z.y * z.y;
+          if (__ballot(q > 0.f && q < 1e-30f) != 0) {
+            z = mag_rescale(z, m);
+          } else {
+            const float f = q > 0.f ? m * __builtin_amdgcn_rsqf(q) : 0.f;
+            z.x *= f;
+            z.y *= f;
+          }
+        }
+        // re-tilt: z conj(t) (S1) or z t (S2), t = exp(-2 pi i h.r/N), times the operand scale
+        const float2 tw = s_tw[(ky * py + kx * px) & (a.L - 1)];
+        const float ti = sc * tw.y, tr = fabsf(sc) * tw.x;
+        v.x = z.x * tr - z.y * ti;
+        v.y = z.x * ti + z.y * tr;
       }
-      if (r < W2) recon_tail(z, m, a.win, W2, r, ec, a.col, a.w);
-      const float2 sv = a.mode == BIP_RECON_MAGNITUDE ? mag_rescale(z, m) : z;
-      const float2 tw = s_tw[(ky * py + kx * px) & (a.L - 1)];  // exp(-2 pi i h.r/N)
-      float2 v = cscale(a.retilt_sign > 0 ? cmulc(sv, tw) : cmul(sv, tw), a.scale);
-      if (!bvalid || r >= W2) v = make_float2(0.f, 0.f);
-      if (bstore && r < n_r) store_planes<PREC>(out, ob + (int64_t)r * KB, plane, v.x, v.y);
+      if (bstore) store_planes<PREC>(obase, (int64_t)i * KB, plane, v.x, v.y);
     }
     __syncthreads();  // slab of rt consumed
     if (rt + 1 < rt_hi) {
@@ -339,7 +363,66 @@ __global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int 
   }
 }
 
+// One atom: a workgroup per beam tile and run of rpw pixel tiles.  Workgroup i
+// runs on XCD i mod 8; each XCD takes a contiguous range of (run, beam tile)
+// pairs, neighbouring beam tiles on the same pixels, so that the parents they
+// share stay in its L2.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_recon_kblk(ReconArgs a, void* out, int nrows, int ncols,
+                                                    int64_t plane, int rpw) {
+  const int nbt = (ncols + TB - 1) / TB, nrt = (nrows + TR - 1) / TR;
+  const int nch = (nrt + rpw - 1) / rpw;
+  const int per = (int)(gridDim.x / 8);
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= nbt * nch) return;
+  const int bt = lin % nbt, ch = lin / nbt;
+  recon_kblk_tile<PREC>(a, out, nrows, ncols, plane, bt, ch * rpw, min(nrt, ch * rpw + rpw));
+}
+
+// Every atom of a chunk in one launch: a workgroup per (atom, beam tile) over
+// all the atom's pixel tiles; an XCD takes a contiguous range of them, so the
+// beam tiles of one atom, which share parents, meet in its L2.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_recon_kblk_atoms(ReconArgs a, const ReconAtom* __restrict__ atoms,
+                                                          int n_atoms, char* out, int ncols,
+                                                          int64_t plane) {
+  const int nbt = (ncols + TB - 1) / TB;
+  const int per = (int)(gridDim.x / 8);
+  const int lin = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (lin >= nbt * n_atoms) return;
+  const int bt = lin % nbt;
+  const ReconAtom at = atoms[lin / nbt];
+  a.win += at.win_off;
+  a.W = at.W;
+  a.oy = at.oy;
+  a.ox = at.ox;
+  constexpr int ES = PREC == BIP_PREC_FP32 ? 4 : 2;
+  recon_kblk_tile<PREC>(a, out + at.out_off * ES, at.n_r, ncols, plane, bt, 0, (at.n_r + TR - 1) / TR);
+}
+
 }  // namespace
+
+hipError_t launch_recon_kblk_atoms(const ReconArgs& a, const ReconAtom* atoms, int n_atoms, void* out,
+                                   int prec, int64_t ncols_pad, int64_t plane_stride, hipStream_t s) {
+  if (n_atoms <= 0 || ncols_pad <= 0) return hipSuccess;
+  if (a.tile_np > TILE_NP || ncols_pad > INT32_MAX) return hipErrorInvalidValue;
+  const int64_t nt = ((ncols_pad + TB - 1) / TB) * n_atoms;
+  const int64_t nblk = (nt + 7) / 8 * 8;
+  if (nblk > INT32_MAX) return hipErrorInvalidValue;
+#define RA(P)                                                                                    \
+  if (prec == P) {                                                                               \
+    hipLaunchKernelGGL((k_recon_kblk_atoms<P>), dim3((unsigned)nblk), dim3(256),                 \
+                       a.L * sizeof(float2), s, a, atoms, n_atoms, (char*)out, (int)ncols_pad,   \
+                       plane_stride);                                                            \
+    return hipGetLastError();                                                                    \
+  }
+  RA(BIP_PREC_FP32)
+  RA(BIP_PREC_SPLIT_BF16)
+  RA(BIP_PREC_BF16)
+  RA(BIP_PREC_FP16)
+#undef RA
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_recon_plain(const ReconArgs& a, float2* out, hipStream_t s) {
   const int64_t n = (int64_t)a.nb * a.W * a.W;
