@@ -239,8 +239,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_profiling(True)
-    plan.stage_timings(reset=True)
+    # the timed steps: no per-stage events inside
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -251,6 +250,17 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    # the same number of steps again with HIP events around every launch, on
+    # the launch stream, for the per-stage times and the kernel rooflines
+    plan.set_profiling(True)
+    plan.stage_timings(reset=True)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    for _ in range(args.steps):
+        step()
+    e3.record()
+    torch.cuda.synchronize()
+    ms_step_profiled = e2.elapsed_time(e3) / args.steps
     stages = plan.stage_timings(reset=True)
     plan.set_profiling(False)
 
@@ -338,6 +348,7 @@ def main():
                      "avg_launch_ms": dom_ms / dom_n},
         "stage_rooflines": per_stage,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "ms_per_step_with_stage_events": ms_step_profiled,
         "multislice": {"algorithmic_GB": ms_bytes / 1e9, "ms_per_step": ms_time,
                        "achieved_GBs": ms_bytes / (ms_time / 1e3) / 1e9,
                        "frac_of_hbm": ms_bytes / (ms_time / 1e3) / 1e9 / HBM_PEAK_GBS},

@@ -360,8 +360,9 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st); }),
          "init S1");
   GatherArgs g1 = gather_args(p, 1);
-  for (int c0 = 0; c0 < p->Bp1; c0 += batch) {
-    const int nc = std::min(batch, p->Bp1 - c0);
+  const int batch1 = balanced_batch(p->Bp1, batch), batch2 = balanced_batch(p->Bp2, batch);
+  for (int c0 = 0; c0 < p->Bp1; c0 += batch1) {
+    const int nc = std::min(batch1, p->Bp1 - c0);
     float2* s1 = p->d_state1 + (int64_t)c0 * G;
     for (int j = 0; j <= p->i_max; ++j) {
       int flags = ROW_GATHER_BEFORE_T;
@@ -385,8 +386,8 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
                                 (float)(1.0 / std::sqrt((double)G)), st); }),
          "init S2");
   GatherArgs g2 = gather_args(p, 2);
-  for (int c0 = 0; c0 < p->Bp2; c0 += batch) {
-    const int nc = std::min(batch, p->Bp2 - c0);
+  for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
+    const int nc = std::min(batch2, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
     HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, s2, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
                            p->d_par2, -1, g2, 0, 0, c0, nullptr, st); }),

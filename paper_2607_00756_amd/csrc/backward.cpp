@@ -403,8 +403,9 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   auto ps = [&](int j) { return p->plane_start[j]; };
   // S1: psi_{j+1} = P(T_j psi_j); windows of plane j come from psi_j
   if (p->i_max > 0) {
-    for (int c0 = 0; c0 < p->Bp1; c0 += batch) {
-      const int nc = std::min(batch, p->Bp1 - c0);
+    const int batch1 = balanced_batch(p->Bp1, batch);
+    for (int c0 = 0; c0 < p->Bp1; c0 += batch1) {
+      const int nc = std::min(batch1, p->Bp1 - c0);
       float2* s1 = p->d_state1 + (int64_t)c0 * G;
       const int grp = std::min(groups, nc);
       const int i = p->i_max;
@@ -424,8 +425,9 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     }
   }
   // S2: v_j = T_j P v_{j+1}; windows of plane j come from v_j
-  for (int c0 = 0; c0 < p->Bp2; c0 += batch) {
-    const int nc = std::min(batch, p->Bp2 - c0);
+  const int batch2 = balanced_batch(p->Bp2, batch);
+  for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
+    const int nc = std::min(batch2, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
     const int grp = std::min(groups, nc);
     for (int j = p->i_min; j < g.nz; ++j) {
