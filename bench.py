@@ -187,16 +187,17 @@ def gradient_leg(steps, warmup):
             "outputs": "dL/dV [nz, ny, nx] and dL/dxyz of every atom (FP64 potential reductions)"}
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, column_batch):
     """HBM bytes per launch of the stage's kernel from the committed counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None
-    when there is none for this stage or the kernel's sources changed since."""
+    when there is none for this stage, it was taken with another column
+    batch, or the kernel's sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("stage") != stage:
+    if t.get("stage") != stage or t.get("column_batch") != column_batch:
         return None
     for src, sha in t.get("sources_sha256", {}).items():
         p = os.path.join(ROOT, src)
@@ -313,7 +314,7 @@ def main():
     launches_per_step = dom_n / args.steps
     amount, unit, bound, peak = work[dom]
     achieved = amount / launches_per_step / (dom_ms / dom_n / 1e3)
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, batch)
     per_stage = {k: {"rate": (w[0] / (stages[k][0] / args.steps / 1e3) if stages[k][0] > 0 else None),
                      "unit": w[1], "bound": w[2], "frac": (w[0] / (stages[k][0] / args.steps / 1e3) / w[3]
                                                             if stages[k][0] > 0 else None)}
