@@ -474,12 +474,13 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   const int64_t csz = (precision == BIP_PREC_BF16 || precision == BIP_PREC_FP16) ? 4 : 8;  // bytes per complex element
   const int planes = precision == BIP_PREC_SPLIT_BF16 ? 4 : 2;
   const int64_t esz = csz / planes;                         // bytes per plane element
-  // The Gram matrix sums |S2~|^2-like products over all n_det detector beams,
-  // which averages the operand rounding: in split mode it runs as single FP16
-  // products (FP32 accumulate), the operand scaled by 2^8 so that its typical
-  // magnitude G^-1/2 ~ 2^-8..2^-10 sits well inside the FP16 normal range; Q is
-  // stored split for the quadratic form, whose rounding does not average.
-  const int gram_prec = precision == BIP_PREC_SPLIT_BF16 ? BIP_PREC_FP16 : precision;
+  // The Gram matrix sums products over all n_det detector beams, which
+  // averages the operand rounding: in split mode with a large detector it runs
+  // as single FP16 products (FP32 accumulate), the operand scaled by 2^8 so
+  // that its typical magnitude G^-1/2 ~ 2^-8..2^-10 sits well inside the FP16
+  // normal range; Q is stored split for the quadratic form, whose rounding does
+  // not average.
+  const int gram_prec = gram_precision(precision, p->ndet);
   const float gram_scale = gram_prec == BIP_PREC_FP16 ? 256.f : 1.f;
   auto kd_of = [](int W) { return roundup((int64_t)W * W, 32); };   // padded window pixels
   auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };  // ... to whole tiles

@@ -76,7 +76,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   // operand precisions: as the forward's map (the Gram matrix on FP16 products
   // of a 2^8-scaled operand in split precision)
   const int prec = precision;
-  const int gprec = prec == BIP_PREC_SPLIT_BF16 ? BIP_PREC_FP16 : BIP_PREC_FP32;
+  const int gprec = gram_precision(prec, p->ndet);
   const float gsc = gprec == BIP_PREC_FP16 ? 256.f : 1.f;
   const int64_t esz = prec == BIP_PREC_FP32 ? 4 : 2, gesz = gprec == BIP_PREC_FP32 ? 4 : 2;
   const int BKF = gemm_bk(gprec);

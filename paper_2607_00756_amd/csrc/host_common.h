@@ -111,6 +111,15 @@ inline int column_batch(int64_t G) {
   if (b <= 0) b = INT32_MAX;
   return (int)std::min<int64_t>(b, INT32_MAX);
 }
+// Split precision runs the Gram matrix on single FP16 products when its sum
+// runs over at least this many detector beams: the FP16 rounding of the
+// operand (2^-11) then averages to well under the 1e-4 target (measured
+// 5e-6 at 32,417 beams); smaller detectors keep the hi+lo BF16 products.
+constexpr int kGramFp16MinBeams = 4096;
+inline int gram_precision(int precision, int ndet) {
+  return precision == BIP_PREC_SPLIT_BF16 && ndet >= kGramFp16MinBeams ? BIP_PREC_FP16 : precision;
+}
+
 // The batch actually used for a sweep over n columns: the fewest batches of
 // at most cap columns, of equal size (the last one at most a column short).
 inline int balanced_batch(int n, int cap) {
