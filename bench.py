@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="split", choices=list(PREC))
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1,
+                    help="specimen (1: the benchmark workload; others for context)")
+    ap.add_argument("--atoms", type=int, default=None,
+                    help="only the first N ionized atoms of the specimen (context runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the timing of the map-loss gradient on the differentiation specimen")
@@ -223,7 +226,7 @@ def main():
     from paper_2607_00756_amd import bip, specimen
 
     dev = torch.device("cuda:0")
-    sp = specimen.make(args.config)
+    sp = specimen.make(args.config, n_ionized=args.atoms)
     cfg = sp.cfg
     plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin)
     V = torch.from_numpy(sp.V).to(dev)
@@ -334,7 +337,7 @@ def main():
                   "bf16": "c64 multislice + bf16 MFMA contraction (f32 accumulate)",
                   "fp16": "c64 multislice + fp16 MFMA contraction (f32 accumulate)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{cfg.name}: FCC 40x40x100 A, {cfg.ny}^2 grid, {cfg.nz} slices, "
+        "config": {"workload": f"{cfg.name}: FCC {cfg.lx:.0f}x{cfg.ly:.0f}x{cfg.lz_cell:.0f} A, {cfg.ny}^2 grid, {cfg.nz} slices, "
                                f"{cfg.energy_ev/1e3:.0f} keV, {cfg.alpha*1e3:.0f}/{cfg.theta*1e3:.0f} mrad, "
                                f"s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
                                f"scan {cfg.scan[0]}x{cfg.scan[1]}, map",
