@@ -1,6 +1,6 @@
 """Throughput of the BiP-PRISM EELS map on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--precision split|fp32|bf16] [--config 1]
+    python bench.py [--steps K] [--warmup W] [--precision split|fp32|bf16|fp16] [--config 1]
 
 One step is the whole hot path on the medium synthetic specimen (FCC a = 3.6 A
 in a 40 x 40 x 100 A cell, 256^2 grid, 50 slices of 2 A, 300 keV, 25 mrad
@@ -38,8 +38,8 @@ PREC = {"fp32": 0, "split": 1, "bf16": 2, "fp16": 3}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="split", choices=list(PREC))
     ap.add_argument("--config", type=int, default=1,
                     help="specimen (1: the benchmark workload; others for context)")
@@ -120,8 +120,17 @@ def cpu_baseline(sp):
         cores = max(cores, blas)
     except Exception:
         pass
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": units / t_full, "unit": "scan-positions*transitions/s", "cores": cores,
+        "cpu_model": model, "os_cpu_count": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"FP64 oracle on config {cfg.name}: parent sweeps of every {step1}th S1/S2 parent "
                    f"({len(p1)}+{len(p2)} of {bip.part1.n_parents}+{bip.part2.n_parents} columns, all "
