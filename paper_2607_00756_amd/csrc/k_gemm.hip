@@ -85,6 +85,23 @@ constexpr int lds_bytes() {
   return nstage<PREC>() * stage_bytes<PREC>();
 }
 
+// The quadratic form's epilogue stages the job's psi^T tile [128 rho][128 r]
+// in LDS once the K loop is done, rows padded by 16 bytes against bank
+// conflicts of the per-lane reads.
+template <int PREC>
+constexpr int quad_row() {
+  return BN + 16 / PT<PREC>::ESZ;
+}
+template <int PREC>
+constexpr int quad_lds_bytes() {
+  return PT<PREC>::PLANES * BM * quad_row<PREC>() * PT<PREC>::ESZ;
+}
+template <int PREC, int EPI>
+constexpr int kernel_lds_bytes() {
+  return (EPI == EPI_QUAD && quad_lds_bytes<PREC>() > lds_bytes<PREC>()) ? quad_lds_bytes<PREC>()
+                                                                         : lds_bytes<PREC>();
+}
+
 // s_waitcnt vmcnt(N) lgkmcnt(0): this wave's loads older than its last N
 // have landed and its LDS reads are complete
 template <int N>
@@ -379,21 +396,37 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
         for (int j = 0; j < 4; ++j)
           sq[i][j] += acc.re[i][j] * acc.re[i][j] + acc.im[i][j] * acc.im[i][j];
     } else if constexpr (EPI == EPI_QUAD) {
-      // Re conj(psi^T[rho][r]) (Q psi)^T[rho][r]; psi is read back from the A operand
+      // Re conj(psi^T[rho][r]) (Q psi)^T[rho][r]; psi is read back from the A
+      // operand: the tile's rows m0.. and columns n0.. (columns below the
+      // row length lda, which K-chunks never straddle) go to LDS in 16-byte
+      // coalesced pieces, then every lane reads its elements from there
+      constexpr int QR = quad_row<PREC>(), QPL = BM * QR, CH = 16 / ESZ;
+      constexpr int NCH = BN / CH;  // 16-byte pieces per row
+      for (int i = tid; i < PT<PREC>::PLANES * BM * NCH; i += NTHREADS) {
+        const int pl = i / (BM * NCH), rem = i - pl * (BM * NCH);
+        const int row = rem / NCH, ch = rem - row * NCH;
+        const int r = n0 + ch * CH;
+        uint4 val = make_uint4(0u, 0u, 0u, 0u);
+        if (r < job.lda)
+          val = *(const uint4*)((const char*)g.A +
+                                (job.a_off + (int64_t)(m0 + row) * job.lda + r + pl * g.a_plane) * ESZ);
+        *(uint4*)(smem + ((int64_t)pl * QPL + row * QR + ch * CH) * ESZ) = val;
+      }
+      __syncthreads();
 #pragma unroll
       for (int bn = 0; bn < 4; ++bn) {
-        const int r = n0 + wn * 64 + bn * 16 + lr;
-        if (r >= job.W2) continue;
+        const int rl = wn * 64 + bn * 16 + lr;  // r - n0
+        if (n0 + rl >= job.W2) continue;
 #pragma unroll
         for (int bm = 0; bm < 4; ++bm)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int rho = m0 + wm * 64 + bm * 16 + kg * 4 + v;
-            const float2 ps =
-                load_planes<PREC>(g.A, job.a_off + (int64_t)rho * job.lda + r, g.a_plane);
+            const int rhol = wm * 64 + bm * 16 + kg * 4 + v;  // rho - m0
+            const float2 ps = load_planes<PREC>(smem, (int64_t)rhol * QR + rl, QPL);
             sq[bm][bn][v] += ps.x * acc.re[bm][bn][v] + ps.y * acc.im[bm][bn][v];
           }
       }
+      __syncthreads();  // the next job's K loop refills LDS
     } else if constexpr (EPI == EPI_STORE) {
       float2* o = (float2*)g.out;
 #pragma unroll
@@ -532,9 +565,10 @@ __global__ void k_qeels(const float* __restrict__ beams_out, const int32_t* __re
 template <int PREC, int EPI, bool CONJA, int OPREC = PREC>
 hipError_t zgemm_launch(const GemmArgs& g, dim3 grid, hipStream_t s) {
   const void* f = (const void*)k_zgemm<PREC, EPI, CONJA, OPREC>;
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes<PREC>());
+  constexpr int lds = kernel_lds_bytes<PREC, EPI>();
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_zgemm<PREC, EPI, CONJA, OPREC>), grid, dim3(NTHREADS), lds_bytes<PREC>(), s, g);
+  hipLaunchKernelGGL((k_zgemm<PREC, EPI, CONJA, OPREC>), grid, dim3(NTHREADS), lds, s, g);
   return hipGetLastError();
 }
 
