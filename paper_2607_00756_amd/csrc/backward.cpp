@@ -20,7 +20,7 @@ namespace bip {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kAdjGroups = 64;  // column groups of the adjoint row pass
+constexpr int kAdjGroups = 32;  // column groups of the adjoint row pass
 
 // parent -> (beam, weight) lists of a CSR beam -> parent weight matrix
 void transpose_csr(const std::vector<int32_t>& rp, const std::vector<int32_t>& col,
