@@ -210,7 +210,8 @@ __global__ void k_dv_reduce(const float* __restrict__ partial, int n_groups, int
 template <int NY>
 struct ColShape {
   static constexpr int T = NY / 16;                       // threads per column transform
-  static constexpr int CB = (NY >= 256) ? 16 : 4096 / NY; // adjacent columns per block
+  // adjacent columns per block (measured: 16 at 256 and 1024, 8 at 512)
+  static constexpr int CB = NY == 512 ? 8 : (NY >= 256) ? 16 : 4096 / NY;
   static constexpr int THREADS = CB * T;
 };
 
