@@ -343,14 +343,24 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   const int lr = lane & 15, kg = lane >> 4;
   int m0, n0, jb0, jb1;
   if constexpr (EPI == EPI_GRAMQ) {
-    // 1-D grid.  Workgroup i runs on XCD i mod 8; all upper-triangle tiles of a
-    // job go to one XCD, so the job's operand rows are shared through its L2.
+    // 1-D grid.  Workgroup i runs on XCD i mod 8.  Small jobs (fewer than 64
+    // tiles) put all their upper-triangle tiles on one XCD, so the job's
+    // operand rows are shared through its L2; the operand of a large job
+    // outgrows the L2 anyway, and its tiles go to consecutive workgroups so
+    // that a chunk of few large jobs still spreads over every XCD.
     const int nt = g.tiles, T = nt * (nt + 1) / 2;
-    const int slot = (int)(blockIdx.x >> 3);
-    jb0 = (slot / T) * 8 + (int)(blockIdx.x & 7);
+    int tl;
+    if (T < 64) {
+      const int slot = (int)(blockIdx.x >> 3);
+      jb0 = (slot / T) * 8 + (int)(blockIdx.x & 7);
+      tl = slot % T;
+    } else {
+      jb0 = (int)blockIdx.x / T;
+      tl = (int)blockIdx.x % T;
+    }
     if (jb0 >= g.njobs) return;  // uniform per workgroup
     jb1 = jb0 + 1;
-    int tl = slot % T, ti = 0;
+    int ti = 0;
     while (tl >= nt - ti) {
       tl -= nt - ti;
       ++ti;
