@@ -107,14 +107,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
  * exp(-2 pi i h_p.r/N).  S2 parents start as G^-1/2 exp(-2 pi i h_p.r/N) and
  * step v <- T_j F^-1[P F[v]] from slice nz-1 down; at each atom's plane
  * (after T_i) the window is cropped and de-tilted by exp(+2 pi i h_p.r/N).
- * Asynchronous: the S1 sweep runs on `stream`, the S2 sweep on a stream the
- * plan owns, after everything enqueued on `stream` so far.  Every call of the
- * plan that reads S2 (bip_eels_signal, bip_reconstruct_local,
- * bip_parent_windows with which = 2, bip_eels_backward, the next
- * bip_build_smatrix) first makes its own stream wait for that sweep, so the
- * usual in-stream ordering holds; synchronizing `stream` right after this
- * call does not by itself wait for the S2 sweep.  Errors: BIP_EINVAL,
- * BIP_EHIP.
+ * Asynchronous on `stream`.  Errors: BIP_EINVAL, BIP_EHIP.
  */
 int bip_build_smatrix(bip_plan* plan, const float* V, void* stream);
 

@@ -142,9 +142,6 @@ const char* bip_last_error(void) { return g_err.c_str(); }
 void bip_plan_destroy(bip_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
-  if (p->s2_stream) (void)hipStreamDestroy(p->s2_stream);
-  if (p->ev_s1) (void)hipEventDestroy(p->ev_s1);
-  if (p->ev_s2) (void)hipEventDestroy(p->ev_s2);
   for (void* a : p->allocations) (void)hipFree(a);
   for (auto& t : p->timed) {
     (void)hipEventDestroy(t.a);
@@ -201,12 +198,6 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   p->nq_half = (int)std::floor(rq + 1e-12);
   p->nq = 2 * p->nq_half + 1;
   int rc = BIP_OK;
-  if (hipStreamCreateWithFlags(&p->s2_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p->ev_s1, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&p->ev_s2, hipEventDisableTiming) != hipSuccess) {
-    bip_plan_destroy(p);
-    return err(BIP_EHIP, "stream or event creation failed");
-  }
   auto fail = [&](int code) {
     bip_plan_destroy(p);
     return code;
@@ -359,8 +350,6 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
-  // a previous build's S2 sweep reads T and owns the S2 state until it ends
-  HIPCHK(hipStreamWaitEvent(st, p->ev_s2, 0), "wait for the previous S2 sweep");
   HIPCHK(timed(p, ST_TRANSMIT, st, [&] { return launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st); }), "transmit");
   // Columns are advanced in batches, every slice of a batch before the next
   // batch, so that a batch (both passes of every slice) can stay resident in
@@ -392,24 +381,19 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
                "S1 column pass");
     }
   }
-  // ---- S2: exit -> shallowest ionization plane (transpose multislice), on
-  // the plan's S2 stream once everything before it on the caller's stream
-  // (T, the S1 sweep, earlier readers of the S2 state) has run
-  HIPCHK(hipEventRecord(p->ev_s1, st), "record");
-  const hipStream_t s2 = p->s2_stream;
-  HIPCHK(hipStreamWaitEvent(s2, p->ev_s1, 0), "wait for S1");
-  HIPCHK(timed(p, ST_INIT, s2, [&] { return launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
-                                (float)(1.0 / std::sqrt((double)G)), s2); }),
+  // ---- S2: exit -> shallowest ionization plane (transpose multislice)
+  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
+                                (float)(1.0 / std::sqrt((double)G)), st); }),
          "init S2");
   GatherArgs g2 = gather_args(p, 2);
   for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
     const int nc = std::min(batch2, p->Bp2 - c0);
-    float2* s2c = p->d_state2 + (int64_t)c0 * G;
-    HIPCHK(timed(p, ST_S2_ROW, s2, [&] { return launch_row_pass(ROW_FWD, s2c, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
-                           p->d_par2, -1, g2, 0, 0, c0, nullptr, s2); }),
+    float2* s2 = p->d_state2 + (int64_t)c0 * G;
+    HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, s2, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
+                           p->d_par2, -1, g2, 0, 0, c0, nullptr, st); }),
            "S2 row transform");
     for (int j = g.nz - 1; j >= p->i_min; --j) {
-      HIPCHK(timed(p, ST_S2_COL, s2, [&] { return launch_col_pass(s2c, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, s2); }),
+      HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
              "S2 column pass");
       int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
       if (j > p->i_min) flags |= ROW_FWD;
@@ -418,12 +402,11 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
         flags |= ROW_SAVE;
         save = p->d_ckpt2 + ((int64_t)(j - p->i_min) * p->Bp2 + c0) * G;
       }
-      HIPCHK(timed(p, ST_S2_ROW, s2, [&] { return launch_row_pass(flags, s2c, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
-                             p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, save, s2); }),
+      HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
+                             p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, save, st); }),
              "S2 row pass");
     }
   }
-  HIPCHK(hipEventRecord(p->ev_s2, s2), "record");
   p->built = true;
   return BIP_OK;
 }
@@ -436,7 +419,6 @@ int bip_parent_windows(bip_plan* p, int32_t atom, int32_t which, float* out, voi
   const int W = p->W[atom];
   const size_t n = (size_t)(which == 1 ? p->Bp1 : p->Bp2) * W * W;
   const float2* src = which == 1 ? p->d_win1 + p->off1[atom] : p->d_win2 + p->off2[atom];
-  if (which == 2) HIPCHK(hipStreamWaitEvent((hipStream_t)stream, p->ev_s2, 0), "wait for S2");
   HIPCHK(hipMemcpyAsync(out, src, n * sizeof(float2), hipMemcpyDeviceToDevice, (hipStream_t)stream),
          "copy windows");
   return BIP_OK;
@@ -448,10 +430,7 @@ int bip_reconstruct_local(bip_plan* p, int32_t atom, float* s1_out, float* s2_ou
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   hipStream_t st = (hipStream_t)stream;
   if (s1_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 1), (float2*)s1_out, st), "recon S1");
-  if (s2_out) {
-    HIPCHK(hipStreamWaitEvent(st, p->ev_s2, 0), "wait for S2");
-    HIPCHK(launch_recon_plain(recon_args(p, atom, 2), (float2*)s2_out, st), "recon S2");
-  }
+  if (s2_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 2), (float2*)s2_out, st), "recon S2");
   return BIP_OK;
 }
 
@@ -734,22 +713,6 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
           off[3][i] + s[3] > pl3)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
-    }
-    // probe synthesis for every atom of the chunk (grid z = atom): S1 only, so
-    // on the first chunk it overlaps the S2 sweep still running on the plan's
-    // S2 stream
-    pa.jobs = d_probe + c0;
-    pa.fx = X;
-    pa.out = gram ? (void*)PsiT : (void*)X2;
-    pa.out_plane = gram ? pl3 : pl2;
-    HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, max_w2, nat, st); }),
-           "probe fold");
-    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),
-           "probe synthesis");
-    if (c == 0) HIPCHK(hipStreamWaitEvent(st, p->ev_s2, 0), "wait for S2");
-    for (int i = c0; i < c1; ++i) {
-      const int a = atoms[i];
-      const int W = p->W[a];
       if (gram && !recon_batched) {
         ReconArgs ra = recon_args(p, a, 2);
         ra.scale = gram_scale;
@@ -774,6 +737,15 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
              }),
              "recon S2 operand");
     }
+    // probe synthesis for every atom of the chunk (grid z = atom)
+    pa.jobs = d_probe + c0;
+    pa.fx = X;
+    pa.out = gram ? (void*)PsiT : (void*)X2;
+    pa.out_plane = gram ? pl3 : pl2;
+    HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, max_w2, nat, st); }),
+           "probe fold");
+    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),
+           "probe synthesis");
     GemmArgs g{};
     g.H = (const float2*)H;
     g.n_ch = n_ch;

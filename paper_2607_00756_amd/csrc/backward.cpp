@@ -68,7 +68,6 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
       return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
   hipStream_t st = (hipStream_t)stream;
-  HIPCHK(hipStreamWaitEvent(st, p->ev_s2, 0), "wait for the S2 sweep");
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
   const int P = scan_sy * scan_sx;

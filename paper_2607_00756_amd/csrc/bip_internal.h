@@ -136,11 +136,6 @@ struct bip_plan {
   std::vector<int32_t> plane_start, plane_atoms;
   int i_min = 0, i_max = 0;
   bool built = false;
-  // The S2 sweep runs on a stream of the plan's own, after the S1 sweep, so
-  // that work on the caller's stream that needs S1 only (the probe synthesis)
-  // overlaps it; every reader of S2 waits for ev_s2 on the caller's stream.
-  hipStream_t s2_stream = nullptr;
-  hipEvent_t ev_s1 = nullptr, ev_s2 = nullptr;
   int column_batch = 0;  // parent columns per sweep batch of the last build
   // device buffers
   float2* d_tw = nullptr;       // [L] exp(-2 pi i m / L)

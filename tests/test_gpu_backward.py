@@ -276,3 +276,20 @@ def test_config4_position_gradient_central_differences(c4):
             # bounded on the scale of the gradient: small components sit at the
             # float32 rounding of the loss
             assert abs(fd - tau[k, c]) <= 1e-3 * max(abs(fd), np.abs(tau).max())
+
+
+def test_backward_with_one_atom_per_workspace_chunk():
+    """A workspace budget too small for two atoms runs the adjoint one atom at
+    a time; dV and dL/dH agree with the default (one batch of all atoms)."""
+    cfg, tp = _ragged(2)
+    r = np.random.default_rng(9)
+    ibar = r.normal(size=cfg.scan[0] * cfg.scan[1]) * 1e-3
+    dV1, gH1, _ = _gpu_grad(cfg, tp, ibar, E.RECON_MAGNITUDE)
+    os.environ["BIP_WORKSPACE_GB"] = "1e-9"
+    try:
+        dV2, gH2, _ = _gpu_grad(cfg, tp, ibar, E.RECON_MAGNITUDE)
+    finally:
+        os.environ.pop("BIP_WORKSPACE_GB", None)
+    e1, e2 = rel_l2(dV2, dV1), rel_l2(gH2, gH1)
+    print(f"[backward chunks] dV {e1:.2e} dH {e2:.2e}")
+    assert e1 < 1e-5 and e2 < 1e-5
