@@ -134,9 +134,24 @@ __device__ inline int lds_index(int idx) {
   return idx * STRIDE + (PAD ? (idx >> 4) : 0);
 }
 
+// Orders the LDS exchange of a stage.  WAVE: every transform lives inside one
+// wavefront (its N/16 lanes are consecutive lanes of one wave), whose LDS
+// instructions execute in issue order, so keeping the compiler from moving
+// LDS accesses across this point is enough; otherwise a workgroup barrier.
+template <bool WAVE>
+__device__ inline void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage.  v: strided-layout registers.  tw: exp(-2 pi i m/L)
 // table; twstep = L / N.
-template <int N, int R, int P, bool LAST, bool INV, int STRIDE, bool PAD>
+template <int N, int R, int P, bool LAST, bool INV, int STRIDE, bool PAD, bool WAVE = false>
 __device__ inline void stage(float2 (&v)[16], float2* lds, int t, const float2* __restrict__ tw,
                              int twstep) {
   constexpr int T = N / 16;
@@ -166,35 +181,37 @@ __device__ inline void stage(float2 (&v)[16], float2* lds, int t, const float2* 
     }
   }
   if (!LAST) {
-    __syncthreads();
+    exchange_sync<WAVE>();
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = lds[lds_index<STRIDE, PAD>(t + T * e)];
-    __syncthreads();
+    exchange_sync<WAVE>();
   }
 }
 
-// Full transform (unnormalized; inverse uses exp(+2 pi i ...)).
-template <int N, bool INV, int STRIDE, bool PAD>
+// Full transform (unnormalized; inverse uses exp(+2 pi i ...)).  WAVE: see
+// exchange_sync (STRIDE 1 with N/16 consecutive lanes per transform).
+template <int N, bool INV, int STRIDE, bool PAD, bool WAVE = false>
 __device__ inline void transform(float2 (&v)[16], float2* lds, int t, const float2* tw, int L) {
+  static_assert(!WAVE || (STRIDE == 1 && N / 16 <= 64), "a wave-synchronized transform must fit one wave");
   const int twstep = L / N;
   if constexpr (N == 64) {
-    stage<64, 16, 1, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<64, 4, 16, true, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
+    stage<64, 16, 1, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<64, 4, 16, true, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
   } else if constexpr (N == 128) {
-    stage<128, 16, 1, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<128, 8, 16, true, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
+    stage<128, 16, 1, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<128, 8, 16, true, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
   } else if constexpr (N == 256) {
-    stage<256, 16, 1, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<256, 16, 16, true, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
+    stage<256, 16, 1, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<256, 16, 16, true, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
   } else if constexpr (N == 512) {
-    stage<512, 16, 1, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<512, 16, 16, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<512, 2, 256, true, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
+    stage<512, 16, 1, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<512, 16, 16, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<512, 2, 256, true, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
   } else {
     static_assert(N == 1024, "unsupported FFT length");
-    stage<1024, 16, 1, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<1024, 16, 16, false, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
-    stage<1024, 4, 256, true, INV, STRIDE, PAD>(v, lds, t, tw, twstep);
+    stage<1024, 16, 1, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<1024, 16, 16, false, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
+    stage<1024, 4, 256, true, INV, STRIDE, PAD, WAVE>(v, lds, t, tw, twstep);
   }
 }
 

@@ -64,14 +64,15 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
                                                   float2* __restrict__ save) {
   using S = RowShape<NX>;
   __shared__ float2 lds[S::ROWS * S::LDS_ROW];
-  extern __shared__ float2 tw[];  // [L] twiddle table: the transforms' barriers order the fill
+  extern __shared__ float2 tw[];  // [L] twiddle table
   __shared__ GatherRec srec[(FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) ? GREC_LDS : 1];
   for (int i = threadIdx.x; i < L; i += 256) tw[i] = twg[i];
   if constexpr ((FLAGS & (ROW_GATHER_BEFORE_T | ROW_GATHER_AFTER_T)) != 0) {
-    // the plane's records are loaded before the state so that their latency
-    // overlaps; the FFT's barriers order them before the gather reads them
     if ((int)threadIdx.x < ge - gb && threadIdx.x < GREC_LDS) srec[threadIdx.x] = ga.rec[gb + threadIdx.x];
   }
+  // the only workgroup barrier: a row and its LDS row belong to one wave, so
+  // the transforms order their exchanges per wave
+  __syncthreads();
   const int t = threadIdx.x % S::T;
   const int f = threadIdx.x / S::T;
   const int y = blockIdx.x * S::ROWS + f;
@@ -82,9 +83,8 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
   float2 v[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) v[e] = row[t + S::T * e];
-  if (FLAGS & ROW_INV) fft::transform<NX, true, 1, true>(v, my_lds, t, tw, L);
+  if (FLAGS & ROW_INV) fft::transform<NX, true, 1, true, true>(v, my_lds, t, tw, L);
   if constexpr ((FLAGS & ROW_GATHER_BEFORE_T) != 0) {
-    if constexpr ((FLAGS & ROW_INV) == 0) __syncthreads();  // no transform barrier before
     if (ge > gb) gather_row<NX>(v, t, y, pcol, ny, ga, srec, gb, ge, parents[pcol], tw, L, sign);
   }
   if (FLAGS & ROW_T) {
@@ -98,11 +98,10 @@ __global__ __launch_bounds__(256) void k_row_pass(float2* __restrict__ state, in
     for (int e = 0; e < 16; ++e) srow[t + S::T * e] = v[e];
   }
   if constexpr ((FLAGS & ROW_GATHER_AFTER_T) != 0) {
-    if constexpr ((FLAGS & ROW_INV) == 0) __syncthreads();
     if (ge > gb) gather_row<NX>(v, t, y, pcol, ny, ga, srec, gb, ge, parents[pcol], tw, L, sign);
   }
   if (FLAGS & ROW_FWD) {
-    fft::transform<NX, false, 1, true>(v, my_lds, t, tw, L);
+    fft::transform<NX, false, 1, true, true>(v, my_lds, t, tw, L);
 #pragma unroll
     for (int e = 0; e < 16; ++e) row[t + S::T * e] = v[e];
   }
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(256) void k_row_adjoint(float2* __restrict__ state,
     float2 v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = (FLAGS & ADJ_ZERO) ? make_float2(0.f, 0.f) : row[t + S::T * e];
-    if constexpr ((FLAGS & ADJ_INV) != 0) fft::transform<NX, true, 1, true>(v, my_lds, t, tw, L);
+    if constexpr ((FLAGS & ADJ_INV) != 0) fft::transform<NX, true, 1, true, true>(v, my_lds, t, tw, L);
     if constexpr ((FLAGS & ADJ_INJ_BEFORE) != 0)
       if (ge > gb) inject_row<NX>(v, t, y, pcol, ny, inj, srec, gb, ge);
     if constexpr ((FLAGS & ADJ_DV) != 0) {
@@ -186,7 +185,7 @@ __global__ __launch_bounds__(256) void k_row_adjoint(float2* __restrict__ state,
     if constexpr ((FLAGS & ADJ_INJ_AFTER) != 0)
       if (ge > gb) inject_row<NX>(v, t, y, pcol, ny, inj, srec, gb, ge);
     if constexpr ((FLAGS & ADJ_FWD) != 0) {
-      fft::transform<NX, false, 1, true>(v, my_lds, t, tw, L);
+      fft::transform<NX, false, 1, true, true>(v, my_lds, t, tw, L);
 #pragma unroll
       for (int e = 0; e < 16; ++e) row[t + S::T * e] = v[e];
     }
