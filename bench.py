@@ -50,6 +50,12 @@ def parse():
                     help="skip the timing of the map-loss gradient on the differentiation specimen")
     ap.add_argument("--grad-only", action="store_true",
                     help="only time the map-loss gradient and print its JSON object")
+    ap.add_argument("--output", default="map", choices=["map", "qeels", "beams"],
+                    help="output of the context run: the map (the benchmark), or the per-beam "
+                         "intensities binned along q_x (qeels) or kept per beam (beams), both "
+                         "through the per-beam detector contraction")
+    ap.add_argument("--progress", action="store_true",
+                    help="synchronize after every step and report it on stderr (long context runs)")
     ap.add_argument("--map-direct", action="store_true",
                     help="map through the per-beam detector contraction instead of the Gram form")
     ap.add_argument("--compare", action="store_true",
@@ -304,13 +310,23 @@ def main():
     V = torch.from_numpy(sp.V).to(dev)
     H = torch.from_numpy(sp.H).to(dev)
     P = cfg.scan[0] * cfg.scan[1]
-    out = torch.empty(P, dtype=torch.float32, device=dev)
+    # per-beam contraction for the direct map and the per-beam outputs
+    direct = args.map_direct or args.output != "map"
+    out_mode = {"qeels": bip.OUT_QEELS, "beams": bip.OUT_BEAMS}.get(
+        args.output, bip.OUT_MAP_DIRECT if args.map_direct else bip.OUT_MAP)
+    out_shape = {"qeels": (P, plan.nq), "beams": (P, plan.ndet)}.get(args.output, (P,))
+    out = torch.empty(out_shape, dtype=torch.float32, device=dev)
     prec = PREC[args.precision]
+
+    n_done = [0]
 
     def step(p=prec, o=out):
         plan.build_smatrix(V)
-        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan,
-                         bip.OUT_MAP_DIRECT if args.map_direct else bip.OUT_MAP, p, o)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, out_mode, p, o)
+        if args.progress:
+            torch.cuda.synchronize()
+            n_done[0] += 1
+            print(f"[step {n_done[0]}] done", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -354,7 +370,7 @@ def main():
     if args.precision == "fp32":
         csz = 8
     elif args.precision == "split":
-        csz = 8 if args.map_direct else 4
+        csz = 8 if direct else 4
     else:
         csz = 4
     mfma_peak = PEAK_TFLOPS[args.precision]
@@ -365,7 +381,7 @@ def main():
         # S2~ written once in the operand planes, parent windows read once
         "recon": (float(np.sum(W2 * (nd * csz + plan.Bp2 * 8))) / 1e9, "GB/s", "hbm", HBM_PEAK_GBS),
     }
-    if args.map_direct:
+    if direct:
         work["det_gemm"] = (float(np.sum(8.0 * nd * W2 * P) * sp.n_ch) / 1e12, "TFLOP/s", "mfma", mfma_peak)
     else:
         work["gram_gemm"] = (float(np.sum(8.0 * W2 * W2 * nd)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
@@ -381,7 +397,7 @@ def main():
              "probe_dft": "k_probe_y (DFT over y, operand store)",
              "recon": "k_recon_operand (S2~ reconstruction)",
              "gram_gemm": "k_zgemm Gram matrix + H correlation",
-             "det_gemm": "k_zgemm detector contraction" if args.map_direct else "k_zgemm quadratic form",
+             "det_gemm": "k_zgemm detector contraction" if direct else "k_zgemm quadratic form",
              "s1_row": "k_row_pass (S1)", "s1_col": "k_col_pass (S1)",
              "s2_row": "k_row_pass (S2)", "s2_col": "k_col_pass (S2)"}
     dom = max(work, key=lambda k: stages[k][0])
@@ -400,7 +416,7 @@ def main():
     ms_bytes = 16.0 * G * col_slices
     ms_time = sum(stages[k][0] for k in ("s1_row", "s1_col", "s2_row", "s2_col")) / args.steps
     res = {
-        "metric": "scan-positions*transitions/s (map, <=1e-4 rel-L2 vs FP64 oracle)",
+        "metric": f"scan-positions*transitions/s ({args.output}, <=1e-4 rel-L2 vs FP64 oracle)",
         "value": value, "unit": "scan-positions*transitions/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
@@ -413,10 +429,10 @@ def main():
         "config": {"workload": f"{cfg.name}: {cfg.lattice.upper()} {cfg.lx:.0f}x{cfg.ly:.0f}x{cfg.lz_cell:.0f} A, {cfg.ny}^2 grid, {cfg.nz} slices, "
                                f"{cfg.energy_ev/1e3:.0f} keV, {cfg.alpha*1e3:.0f}/{cfg.theta*1e3:.0f} mrad, "
                                f"s={cfg.partition}, {n_atoms} atoms x {sp.n_ch} channels, "
-                               f"scan {cfg.scan[0]}x{cfg.scan[1]}, map",
+                               f"scan {cfg.scan[0]}x{cfg.scan[1]}, {args.output}",
                    "units_per_step": units, "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1,
                    "Bp2": plan.Bp2, "W": int(sp.win_size[0]), "precision": args.precision,
-                   "map_contraction": "direct" if args.map_direct else "gram",
+                   "map_contraction": "direct" if direct else "gram",
                    "column_batch": int(plan.query(bip.Q_SCALARS)[2])},
         "roofline": {"bound": bound, "kernel": names[dom], "stage": dom,
                      "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
