@@ -202,6 +202,12 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     bip_plan_destroy(p);
     return code;
   };
+  {
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n_cu > 0)
+      p->n_cu = n_cu;
+  }
   if (p->B < 1 || p->ndet < 1) return fail(err(BIP_EINVAL, "empty aperture or detector"));
   if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
   if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
@@ -776,9 +782,9 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       u.jobs = d_jquad + c0;
       u.njobs = nat;
       u.partial = partial;
-      // enough job groups to fill the chip; partial rows reduced in a fixed order
+      // job groups that fill the chip evenly; partial rows reduced in a fixed order
       const int qt = (int)(Ppad / 128) * (max_n1 / 128);
-      u.zsplit = std::max(1, std::min({GEMM_MAX_ZSPLIT, nat, (1024 + qt - 1) / qt}));
+      u.zsplit = quad_groups(qt, nat, p->n_cu);
       HIPCHK(timed(p, ST_DET, st, [&] {
                return launch_zgemm(precision, EPI_QUAD, u, (int)(Ppad / 128), max_n1 / 128, u.zsplit, st);
              }),

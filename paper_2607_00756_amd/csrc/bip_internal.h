@@ -137,6 +137,7 @@ struct bip_plan {
   int i_min = 0, i_max = 0;
   bool built = false;
   int column_batch = 0;  // parent columns per sweep batch of the last build
+  int n_cu = 256;        // compute units of the plan's device
   // device buffers
   float2* d_tw = nullptr;       // [L] exp(-2 pi i m / L)
   float2* d_prop = nullptr;     // [ny][nx] P(q) / G

@@ -128,6 +128,23 @@ inline int balanced_batch(int n, int cap) {
   return (int)((n + nb - 1) / nb);
 }
 
+// Job groups of the quadratic form.  Its workgroups hold a CU each (LDS), so
+// qt tiles x z groups run in ceil(qt z / n_cu) rounds of ceil(nat / z) jobs
+// per workgroup: take the z with the fewest job-rounds, the smallest on ties
+// (fewer partial rows to reduce).
+inline int quad_groups(int qt, int nat, int n_cu) {
+  int best = 1;
+  int64_t cost = INT64_MAX;
+  for (int z = 1; z <= std::min(GEMM_MAX_ZSPLIT, nat); ++z) {
+    const int64_t c = ((int64_t)qt * z + n_cu - 1) / n_cu * ((nat + z - 1) / z);
+    if (c < cost) {
+      cost = c;
+      best = z;
+    }
+  }
+  return best;
+}
+
 inline GatherArgs gather_args(const bip_plan* p, int side) {
   GatherArgs g;
   g.rec = side == 1 ? p->d_grec1 : p->d_grec2;
