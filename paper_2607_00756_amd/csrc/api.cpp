@@ -387,17 +387,15 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
                "S1 column pass");
     }
   }
-  // ---- S2: exit -> shallowest ionization plane (transpose multislice)
-  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw, p->L, -1,
-                                (float)(1.0 / std::sqrt((double)G)), st); }),
+  // ---- S2: exit -> shallowest ionization plane (transpose multislice).  The
+  // parents start row-transformed, the form the state keeps between passes.
+  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves_rowft(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw,
+                                p->L, (float)(1.0 / std::sqrt((double)G)), st); }),
          "init S2");
   GatherArgs g2 = gather_args(p, 2);
   for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
     const int nc = std::min(batch2, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
-    HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(ROW_FWD, s2, nc, g.ny, g.nx, nullptr, p->d_tw, p->L,
-                           p->d_par2, -1, g2, 0, 0, c0, nullptr, st); }),
-           "S2 row transform");
     for (int j = g.nz - 1; j >= p->i_min; --j) {
       HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
              "S2 column pass");

@@ -208,6 +208,9 @@ hipError_t launch_prop_table(float2* prop, int ny, int nx, double ly, double lx,
 hipError_t launch_transmit(float2* T, const float* V, int64_t n, float sigma, hipStream_t s);
 hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, int nx,
                                   const float2* tw, int L, int sign, float scale, hipStream_t s);
+// sign -1 plane waves written row-transformed (the state between passes)
+hipError_t launch_init_planewaves_rowft(float2* state, const int2* h, int nb, int ny, int nx,
+                                        const float2* tw, int L, float scale, hipStream_t s);
 hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p, double* slot_w,
                          hipStream_t st);
 

@@ -84,6 +84,30 @@ hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, 
   return hipGetLastError();
 }
 
+// The same plane waves with sign -1, already row-transformed: the forward
+// row DFT of scale exp(-2 pi i (h_y y/ny + h_x x/nx)) is scale nx
+// exp(-2 pi i h_y y/ny) at k_x = -h_x (mod nx) and zero at every other k_x.
+__global__ void k_init_planewaves_rowft(float2* state, const int2* __restrict__ h, int ny, int nx,
+                                        const float2* __restrict__ tw, int L, float scale) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  int y = blockIdx.y;
+  int p = blockIdx.z;
+  if (x >= nx) return;
+  int2 hp = h[p];
+  const int kx = ((-hp.y) % nx + nx) % nx;
+  float2 v = make_float2(0.f, 0.f);
+  if (x == kx) v = cscale(tw[(hp.x * y * (L / ny)) & (L - 1)], scale * (float)nx);
+  state[((size_t)p * ny + y) * nx + x] = v;
+}
+
+hipError_t launch_init_planewaves_rowft(float2* state, const int2* h, int nb, int ny, int nx,
+                                        const float2* tw, int L, float scale, hipStream_t s) {
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_planewaves_rowft, dim3((nx + 255) / 256, ny, nb), dim3(256), 0, s, state,
+                     h, ny, nx, tw, L, scale);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Sibson
 // Natural-neighbour (Sibson) coordinates of a query beam x against the
 // infinite parent lattice s Z^2 (eq. nnw): w_p = |V+(x) ∩ V(p)| / |V+(x)|,
