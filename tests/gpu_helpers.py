@@ -36,6 +36,10 @@ def gpu_run(cfg, V, tau, win_size, win_origin, H, H_off, n_ch, out_mode, precisi
 
 
 def rel_l2(x, ref):
-    x = np.asarray(x, np.float64)
-    ref = np.asarray(ref, np.float64)
+    """||x - ref|| / ||ref|| over the whole array; complex inputs are compared
+    as complex128 (real and imaginary parts both count)."""
+    x, ref = np.asarray(x), np.asarray(ref)
+    assert x.shape == ref.shape, (x.shape, ref.shape)
+    dt = np.complex128 if (np.iscomplexobj(x) or np.iscomplexobj(ref)) else np.float64
+    x, ref = x.astype(dt), ref.astype(dt)
     return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
