@@ -66,6 +66,8 @@ def parse():
                     help="context run: split the ionized atoms into K groups, each with a plan of "
                          "its own that sweeps the parents once for its atoms (a workload whose "
                          "window stacks do not fit one plan), maps summed over the groups")
+    ap.add_argument("--no-fullmap", action="store_true",
+                    help="skip the full-map workload leg (512^2, 100 slices, 2000 atoms x 3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times and exit: the known "
                          "byte count that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -207,6 +209,59 @@ def gradient_leg(steps, warmup):
             "ms_per_gradient": ms, "ms_forward": fwd_ms / steps, "ms_backward": ms - fwd_ms / steps,
             "steps": steps, "precision": "split (FP16 Gram, hi+lo BF16 products)",
             "outputs": "dL/dV [nz, ny, nx] and dL/dxyz of every atom (FP64 potential reductions)"}
+
+
+def full_map_leg(precision="split", steps=1, warmup=1):
+    """The largest workload on one GPU: 80 x 80 x 200 A two-species FCC, 512^2
+    grid, 100 slices, 300 keV, 30/60 mrad, s = 6, 2000 ionized atoms x 3
+    channels with 24^2..64^2 windows, scan 128 x 128, map.  One plan: the S1
+    windows of every atom stay resident, S2 is swept in plane segments inside
+    the signal call (its windows of all atoms would take 187 GB).  Timed steps
+    of build + signal after untimed warmups (HIP events on the stream)."""
+    import torch
+    from paper_2607_00756_amd import bip, specimen
+
+    dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
+    sp = specimen.make(2)
+    cfg = sp.cfg
+    plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin)
+    V = torch.from_numpy(sp.V).to(dev)
+    H = torch.from_numpy(sp.H).to(dev)
+    P = cfg.scan[0] * cfg.scan[1]
+    out = torch.empty(P, dtype=torch.float32, device=dev)
+    prec = PREC[precision]
+    t_setup = time.perf_counter() - t_setup
+
+    def step():
+        plan.build_smatrix(V)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, prec, out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sc = plan.query(bip.Q_SCALARS)
+    mem = plan.query(bip.Q_MEMORY)
+    units = P * len(sp.tau) * sp.n_ch
+    res = {"workload": f"{cfg.name}: FCC two-species {cfg.lx:.0f}x{cfg.ly:.0f}x{cfg.lz_cell:.0f} A, "
+                       f"{cfg.ny}^2 grid, {cfg.nz} slices, {cfg.energy_ev/1e3:.0f} keV, "
+                       f"{cfg.alpha*1e3:.0f}/{cfg.theta*1e3:.0f} mrad, s={cfg.partition}, "
+                       f"{len(sp.tau)} atoms x {sp.n_ch} channels (W 24..64), scan "
+                       f"{cfg.scan[0]}x{cfg.scan[1]}, map",
+           "value": units / (ms / 1e3), "unit": "scan-positions*transitions/s", "ms_per_step": ms,
+           "steps": steps, "warmup": warmup, "precision": precision, "units_per_step": units,
+           "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1, "Bp2": plan.Bp2,
+           "s2_plane_segments": int(sc[3]), "plan_device_GB": float(mem[1]) / 1e9,
+           "setup_s": t_setup, "map_sum": float(out.double().sum().item())}
+    plan.close()
+    return res
 
 
 def measured_traffic(stage, column_batch):
@@ -388,10 +443,13 @@ def main():
         work["det_gemm"] = (float(np.sum(8.0 * W2 * W2 * P)) / 1e12, "TFLOP/s", "mfma", mfma_peak)
     # parent sweeps: every pass reads and writes the whole state of the columns
     # of its batch; launches_per_step / n_batches passes over all columns
+    # algorithmic bytes of a slice step are 16 G per column (the state read once
+    # and written once); a step runs as two passes (rows, then columns), so each
+    # pass is credited with half of it, 8 G per column of its batch
     batch = int(plan.query(bip.Q_SCALARS)[2])
     for st, ncol in (("s1_row", plan.Bp1), ("s1_col", plan.Bp1), ("s2_row", plan.Bp2), ("s2_col", plan.Bp2)):
         n_batches = -(-ncol // batch)
-        work[st] = (16.0 * G * ncol * stages[st][1] / args.steps / n_batches / 1e9, "GB/s", "hbm",
+        work[st] = (8.0 * G * ncol * stages[st][1] / args.steps / n_batches / 1e9, "GB/s", "hbm",
                     HBM_PEAK_GBS)
     names = {"probe_fold": "k_probe_fold_x (S1~ reconstruction + residue fold + DFT over x)",
              "probe_dft": "k_probe_y (DFT over y, operand store)",
@@ -438,7 +496,13 @@ def main():
                      "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                      "traffic": traffic, "traffic_unit": "bytes per launch (HBM, counters)",
                      "launches_per_step": launches_per_step,
-                     "avg_launch_ms": dom_ms / dom_n},
+                     "avg_launch_ms": dom_ms / dom_n,
+                     "algorithmic_per_launch": amount / launches_per_step * (1e9 if unit == "GB/s" else 1e12),
+                     # the rate of the bytes the counters saw move (both passes move the
+                     # whole state), beside the algorithmic rate
+                     "counter_rate": (traffic / (dom_ms / dom_n / 1e3) / 1e9 if traffic else None),
+                     "counter_frac": (traffic / (dom_ms / dom_n / 1e3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic else None)},
         "stage_rooflines": per_stage,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "ms_per_step_with_stage_events": ms_step_profiled,
@@ -463,8 +527,11 @@ def main():
                            "rel_l2_vs_" + args.precision: float(torch.linalg.norm(o2 - ref) / torch.linalg.norm(ref))}
         res["other_precisions"] = other
     plan.close()
+    del plan, V, H, out
     if not args.no_grad:
         res["gradient"] = gradient_leg(args.steps, args.warmup)
+    if not args.no_fullmap and args.config == 1 and args.atoms is None:
+        res["full_map_workload"] = full_map_leg(args.precision)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sp)
     print(json.dumps(res))

@@ -64,12 +64,42 @@ typedef struct bip_optics {
   double theta_rad;     /* collection semi-angle: detector |q| <= theta/lambda        */
   int32_t partition;    /* parent lattice factor s >= 1 (s = 1: exact PRISM)         */
   int32_t recon_mode;   /* BIP_RECON_MAGNITUDE (eq. magpreserve) or BIP_RECON_COMPLEX */
-  int32_t ckpt_stride;  /* 0: forward only; 1: bip_build_smatrix also keeps the
-                           transmitted state of every parent column at every slice
-                           (slice checkpoints) so that bip_eels_backward can run */
+  int32_t ckpt_stride;  /* 0: forward only; k >= 1: bip_build_smatrix also keeps the
+                           transmitted state of every parent column at every k-th
+                           slice (slice checkpoints) so that bip_eels_backward can
+                           run; it recomputes the other slices of a segment from
+                           its checkpoint (k = 1: nothing recomputed) */
+  double s2_window_gb;  /* budget of the S2 window stacks (GiB; 0 = 48).  When the
+                           windows of all atoms exceed it, the S2 sweep runs inside
+                           bip_eels_signal in plane segments whose windows fit the
+                           budget, each segment's atoms contracted before the next
+                           segment is swept (one sweep per signal call) */
 } bip_optics;
 
 typedef struct bip_plan bip_plan;
+
+/*
+ * bip_alloc -- device memory callbacks (optional).  Passage: the problem
+ * statement of Algs. 4/5 ("Require") names the inputs; where their working
+ * memory comes from is the caller's choice, so that e.g. a framework's
+ * caching allocator serves it.
+ *   alloc    returns `bytes` of device memory usable in stream order on
+ *            `stream` (the hipStream_t of the call that allocates), or NULL
+ *            on failure (the call then returns BIP_ENOMEM).
+ *   release  gives back a block from alloc (same size and stream); the
+ *            library calls it in stream order: work queued on `stream`
+ *            before the call may still use the block, none after it.
+ *   ctx      passed through unchanged.
+ * With a NULL bip_alloc the library uses hipMallocAsync / hipFreeAsync on
+ * the call's stream.  A plan's blocks are made on the stream of the call
+ * that needs them; using one plan from several streams at once is not
+ * supported.
+ */
+typedef struct bip_alloc {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*release)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} bip_alloc;
 
 /*
  * bip_plan_create -- geometry and workspace for one specimen.
@@ -84,17 +114,21 @@ typedef struct bip_plan bip_plan;
  *                  W % 4 == 0).
  *   win_origin     host i32 [n_atoms][2] window origin (oy, ox) in pixels,
  *                  taken mod N; the window wraps periodically.
- * Computes on the GPU, in FP64: aperture and detector beams, the Sibson
- * weights of every beam on the parent lattice s Z^2, and the propagator
- * phase table.  Parents are the lattice points with a weight > 1e-12 for
- * some beam.  Allocates all device workspace of the plan (parent columns,
- * window stacks).  Synchronizes `stream` once (to size the parent sets).
- * Errors: BIP_EINVAL (shapes/ranges), BIP_EUNSUPPORTED (aperture or detector
- * beyond Nyquist, parents outside the grid), BIP_ENOMEM, BIP_EHIP.
+ *   alloc          host struct (copied) or NULL: where every device block of
+ *                  the plan comes from (plan tables, parent columns, window
+ *                  stacks, checkpoints, workspaces of later calls).
+ * Aperture and detector beams are enumerated on the host (q^2 <= (angle /
+ * lambda)^2 in FP64, sorted by (h_y, h_x)); the Sibson weights of every beam
+ * on the parent lattice s Z^2 and the propagator phase table are computed on
+ * the GPU in FP64.  Parents are the lattice points with a weight > 1e-12 for
+ * some beam.  Synchronizes `stream` (to size the parent sets).
+ * Errors: BIP_EINVAL (shapes/ranges), BIP_EUNSUPPORTED (a parent outside the
+ * signed index range [-N/2, N/2) of the grid, which would alias),
+ * BIP_ENOMEM, BIP_EHIP.
  */
 int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_atoms,
                     const double* tau_xyz, const int32_t* win_size, const int32_t* win_origin,
-                    void* stream, bip_plan** out);
+                    const bip_alloc* alloc, void* stream, bip_plan** out);
 
 /*
  * bip_build_smatrix -- step (a): parent sweeps and window gathers.
@@ -164,7 +198,7 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
  * a5..a14).  Passage: the forward model's multislice (eq. smatrix-advance,
  * eq. s2), eq. window-recon / eq. magpreserve and eq. coupling / eq. map-sum,
  * differentiated by hand in reverse order.
- * Requires a plan created with ckpt_stride = 1 and a bip_build_smatrix of the
+ * Requires a plan created with ckpt_stride >= 1 and a bip_build_smatrix of the
  * same V: the reverse sweeps read the slice checkpoints it kept.  All atoms
  * of the plan contribute; the map is the one bip_eels_signal returns for
  * out_mode BIP_OUT_MAP with the same H and raster.  The contraction and its
@@ -180,9 +214,9 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
  *              derivative dL/d conj(H_n(r)) (dL = 2 Re sum conj(g) dH).
  *   dHdx, dHdy device complex64, ragged like H, or NULL: dH/dtau_x, dH/dtau_y
  *              of each atom's transition potentials on its window.
- *   dL_dtau_xy host f64 [n_atoms][2] or NULL (needs dHdx, dHdy): the position
- *              gradient through the transition potentials, 2 Re sum conj(g) dH/dtau;
- *              when given, the call synchronizes the stream.
+ *   dL_dtau_xy device f64 [n_atoms][2] or NULL (needs dHdx, dHdy): the
+ *              position gradient through the transition potentials,
+ *              2 Re sum conj(g) dH/dtau.
  * The position gradient through the slice potentials is bip_potential_grad
  * of dL_dV.  Deterministic: no atomics, fixed reduction orders.
  * Errors: BIP_EINVAL, BIP_ESTATE (no build, or no checkpoints),
@@ -201,22 +235,27 @@ int bip_eels_backward(bip_plan* plan, int32_t n_ch, const float* H, const int64_
  * (clamped), periodic images out to 10 width[k]; evaluated in FP64.
  *   xyz    host f64 [n_atoms][3] (x, y, z) in A.
  *   amp    host f64 [n_atoms][n_terms] in V*A; width host f64 [n_terms] in A.
+ *   alloc  as for bip_plan_create (its temporaries), or NULL.
  *   V      device f32 [nz][ny][nx], overwritten.
- * Allocates temporary device memory and synchronizes the stream.
+ * Asynchronous on `stream`: the host arrays are copied before the call
+ * returns; the temporaries are released in stream order.
  */
 int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
-                        const double* amp, const double* width, float* V, void* stream);
+                        const double* amp, const double* width, float* V, const bip_alloc* alloc,
+                        void* stream);
 
 /*
  * bip_potential_grad -- dL/dxyz of every atom from dL/dV (the adjoint of
  * bip_potential_build): dL/dx_a = sum_r dL/dV_j(r) dv_a(r)/dx_a, likewise y;
- * dL/dz = 0 (slice membership is piecewise constant).
- *   dL_dV    device f32 [nz][ny][nx];  dL_dxyz  host f64 [n_atoms][3], overwritten.
- * Allocates temporary device memory and synchronizes the stream.
+ * dL/dz = 0 (slice membership is piecewise constant).  FP64 reductions in a
+ * fixed order (bitwise reproducible).
+ *   dL_dV    device f32 [nz][ny][nx];
+ *   dL_dxyz  device f64 [n_atoms][3], overwritten.
+ * Asynchronous on `stream`, like bip_potential_build.
  */
 int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
                        const double* amp, const double* width, const float* dL_dV,
-                       double* dL_dxyz, void* stream);
+                       double* dL_dxyz, const bip_alloc* alloc, void* stream);
 
 /*
  * bip_parent_windows -- the cropped, de-tilted parent windows gathered by
@@ -236,8 +275,11 @@ enum {
   BIP_Q_WEIGHTS1 = 6, /* CSR of w(1): i32 rowptr[B+1], i32 col[nnz1], f64 w[nnz1] packed
                          back to back in that order (host buffer)             */
   BIP_Q_WEIGHTS2 = 7, /* same for the detector weights w(2)                   */
-  BIP_Q_SCALARS = 8   /* f64[4]: lambda (A), sigma (rad/(V A)), parent columns per
-                         sweep batch of the last bip_build_smatrix (0 before), 0 */
+  BIP_Q_SCALARS = 8,  /* f64[4]: lambda (A), sigma (rad/(V A)), parent columns per
+                         sweep batch of the last sweep (0 before), number of S2
+                         plane segments (0: S2 windows resident) */
+  BIP_Q_MEMORY = 9    /* i64[3]: device bytes the plan holds now, the most it has
+                         held, and the number of blocks it holds */
 };
 
 /* bip_query -- copy plan metadata into the host buffer `out`. */
@@ -268,7 +310,8 @@ enum {
 };
 int bip_stage_timings(bip_plan* plan, double* ms, int64_t* launches, int32_t reset);
 
-/* bip_plan_destroy -- synchronizes and frees every device buffer of the plan. */
+/* bip_plan_destroy -- synchronizes the stream of the plan's last call and
+ * releases every device block of the plan (through its bip_alloc). */
 void bip_plan_destroy(bip_plan* plan);
 
 /* bip_last_error -- message of the last failure on this thread ("" if none). */

@@ -142,7 +142,7 @@ class MapGradient:
             psi = S1.T @ C.T                                       # [K, P]
             amp = np.stack([S2 @ (H[n][:, None] * psi) for n in range(prob.n_ch)])  # [n, d, P]
             I += np.sum(amp.real ** 2 + amp.imag ** 2, axis=(0, 1))
-            per[a] = (y, x, S1, S2, H, psi, amp, st1, st2)
+            per[a] = (y, x, S1, S2, H, psi, st1, st2)   # amp is recomputed below (memory)
         L = float(np.sum((I - I_target) ** 2))
         Ibar = 2.0 * (I - I_target)                                # dL/dI
         # ---- contraction, probe and reconstruction adjoints per atom
@@ -150,7 +150,9 @@ class MapGradient:
         inj2 = {}
         gH_all, dtau = {}, {}
         for a in atoms:
-            y, x, S1, S2, H, psi, amp, st1, st2 = per[a]
+            y, x, S1, S2, H, psi, st1, st2 = per[a]
+            per[a] = None
+            amp = np.stack([S2 @ (H[n][:, None] * psi) for n in range(prob.n_ch)])  # as above
             W = len(y)
             g_amp = Ibar[None, None, :] * amp                      # dL/d conj(a)
             g_psi = np.zeros_like(psi)

@@ -252,20 +252,17 @@ class BiP:
         self.recon_mode = recon_mode
 
     def parent_windows(self, atoms):
-        """{atom: (S1 parent windows [Bp1, W, W], S2 parent windows [Bp2, W, W])}."""
+        """{atom: (S1 parent windows [Bp1, W, W], S2 parent windows [Bp2, W, W])}.
+
+        The parent columns are propagated in batches and cropped to each
+        window as the sweep passes its plane (memory of the windows only)."""
         prob = self.prob
         cfg = prob.cfg
-        planes = sorted(set(int(prob.planes[a]) for a in atoms))
-        out = {}
-        # propagate parents plane by plane, cropping as we go (memory-light)
-        S1 = ms.s1_at_planes(cfg, self.part1.parents, prob.T, prob.P, planes)
-        for a in atoms:
-            out[a] = [prob.crop(S1[int(prob.planes[a])], a), None]
-        del S1
-        S2 = ms.s2_at_planes(cfg, self.part2.parents, prob.T, prob.P, planes)
-        for a in atoms:
-            out[a][1] = prob.crop(S2[int(prob.planes[a])], a)
-        return out
+        atoms = list(atoms)
+        wins = [(int(prob.planes[a]),) + tuple(prob.window(a)) for a in atoms]
+        w1 = ms.s1_windows(cfg, self.part1.parents, prob.T, prob.P, wins)
+        w2 = ms.s2_windows(cfg, self.part2.parents, prob.T, prob.P, wins)
+        return {a: [w1[k], w2[k]] for k, a in enumerate(atoms)}
 
     def reconstructed(self, a, pw):
         """(S1~ [B, W, W], S2~ [n_det, W, W]) on the window of atom a."""
@@ -277,7 +274,14 @@ class BiP:
                          self.recon_mode)
         return s1, s2
 
-    def run(self, mode=OUT_MAP, atoms=None, order="probe", scans=None, per_atom=False):
+    def run(self, mode=OUT_MAP, atoms=None, order="probe", scans=None, per_atom=False,
+            rows=None, progress=None):
+        """Outputs of Alg. 5 summed over `atoms` (input order) at the scan
+        positions `scans` (indices into the raster; None = all).
+
+        rows: when given, the detector beams are reconstructed and contracted
+        rows at a time (each beam's intensity is computed alone, so this only
+        bounds the memory of S2~)."""
         prob = self.prob
         atoms = _atoms(prob, atoms)
         pw = self.parent_windows(atoms)
@@ -288,11 +292,25 @@ class BiP:
         I_dp = np.zeros((len(prob.det), C.shape[0]))
         parts = {}
         for a in atoms:
-            s1, s2 = self.reconstructed(a, pw[a])
-            Ia = contract(s1, s2, prob.H_atom(a), C)
+            if rows is None:
+                s1, s2 = self.reconstructed(a, pw[a])
+                Ia = contract(s1, s2, prob.H_atom(a), C)
+            else:
+                y, x = prob.window(a)
+                s1 = reconstruct(prob.cfg, pw[a][0], self.part1.parents, self.part1.W, prob.beams,
+                                 y, x, 1, self.recon_mode)
+                Ia = np.zeros_like(I_dp)
+                for d0 in range(0, len(prob.det), rows):
+                    d1 = min(d0 + rows, len(prob.det))
+                    s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W[d0:d1],
+                                     prob.det[d0:d1], y, x, 2, self.recon_mode)
+                    Ia[d0:d1] = contract(s1, s2, prob.H_atom(a), C)
             if per_atom:
                 parts[a] = Ia
             I_dp += Ia
+            pw[a] = None
+            if progress:
+                progress(a)
         out = reduce_output(prob.cfg, I_dp, prob.det, mode)
         return (out, parts) if per_atom else out
 

@@ -97,6 +97,48 @@ def s2_at_planes(cfg, beams, T, P, planes, batch=256):
     return out
 
 
+def _crop(cols, y, x):
+    return cols[:, y[:, None], x[None, :]]
+
+
+def s1_windows(cfg, beams, T, P, wins, batch=64):
+    """S1 columns cropped to windows as the sweep passes their planes.
+
+    wins: list of (plane i, y pixels, x pixels); returns one [n, W, W] array
+    per window, holding S1 after slices 0..i-1 on that window.  The same
+    steps as s1_at_planes, but no full column is kept beyond the batch being
+    advanced, so the memory is that of the windows."""
+    out = [np.empty((len(beams), len(y), len(x)), np.complex128) for (_, y, x) in wins]
+    order = sorted(range(len(wins)), key=lambda k: wins[k][0])
+    for b0 in range(0, len(beams), batch):
+        S = initial_s1(cfg, beams[b0:b0 + batch])
+        j = 0
+        for k in order:
+            i, y, x = wins[k]
+            while j < i:
+                S = step(S, T[j], P)
+                j += 1
+            out[k][b0:b0 + len(S)] = _crop(S, y, x)
+    return out
+
+
+def s2_windows(cfg, beams, T, P, wins, batch=64):
+    """S2 columns cropped to windows as the transpose sweep passes their
+    planes (counterpart of s1_windows; S2 at plane i carries slices i..N_Z-1)."""
+    out = [np.empty((len(beams), len(y), len(x)), np.complex128) for (_, y, x) in wins]
+    order = sorted(range(len(wins)), key=lambda k: -wins[k][0])
+    for b0 in range(0, len(beams), batch):
+        S = initial_s2(cfg, beams[b0:b0 + batch])
+        j = T.shape[0] - 1
+        for k in order:
+            i, y, x = wins[k]
+            while j >= i:
+                S = transpose_step(S, T[j], P)
+                j -= 1
+            out[k][b0:b0 + len(S)] = _crop(S, y, x)
+    return out
+
+
 def s2_peeled(cfg, beams, T, P, planes):
     """S2 at each plane obtained by building it at the entrance (plane 0) and
     peeling forward one slice at a time with the inverse transpose step

@@ -24,7 +24,7 @@ RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
 OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT = 0, 1, 2, 3
 PREC_FP32, PREC_SPLIT_BF16, PREC_BF16, PREC_FP16 = 0, 1, 2, 3
 Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
-    Q_SCALARS = range(9)
+    Q_SCALARS, Q_MEMORY = range(10)
 
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
@@ -42,12 +42,81 @@ class BipGrid(ctypes.Structure):
 class BipOptics(ctypes.Structure):
     _fields_ = [("energy_ev", ctypes.c_double), ("alpha_rad", ctypes.c_double),
                 ("theta_rad", ctypes.c_double), ("partition", ctypes.c_int32),
-                ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32)]
+                ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32),
+                ("s2_window_gb", ctypes.c_double)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class BipAlloc(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """bip_alloc callbacks served by torch's caching allocator on the current
+    device, in the order of the stream the library passes.  Counts what goes
+    through it (live bytes and blocks, total allocations)."""
+
+    def __init__(self):
+        self.device = None  # the current device at the first allocation
+        self.live = {}
+        self.n_alloc = 0
+        self.failed = 0
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                if self.device is None:
+                    self.device = torch.cuda.current_device()
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:  # out of memory: the library returns BIP_ENOMEM
+                self.failed += 1
+                return None
+            self.live[ptr] = int(nbytes)
+            self.n_alloc += 1
+            return ptr
+
+        def _release(ptr, nbytes, stream, ctx):
+            try:
+                if ptr:
+                    self.live.pop(ptr, None)
+                    torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch may be gone already
+                pass
+
+        self._fns = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))  # kept alive with the object
+        self.struct = BipAlloc(self._fns[0], self._fns[1], None)
+
+    @property
+    def live_bytes(self):
+        return sum(self.live.values())
+
+
+_default_allocator = None
+
+
+def default_allocator():
+    """One TorchAllocator per process (plans and potential helpers share it)."""
+    global _default_allocator
+    if _default_allocator is None:
+        _default_allocator = TorchAllocator()
+    return _default_allocator
+
+
+def _alloc_arg(allocator):
+    """"torch" (default) -> the shared TorchAllocator; None -> the library's own
+    stream-ordered HIP pool; or a TorchAllocator instance."""
+    if allocator == "torch":
+        allocator = default_allocator()
+    if allocator is None:
+        return None, None
+    return allocator, ctypes.byref(allocator.struct)
 
 
 _p = ctypes.c_void_p
 _lib.bip_plan_create.argtypes = [ctypes.POINTER(BipGrid), ctypes.POINTER(BipOptics), ctypes.c_int32,
-                                 _p, _p, _p, _p, ctypes.POINTER(_p)]
+                                 _p, _p, _p, _p, _p, ctypes.POINTER(_p)]
 _lib.bip_build_smatrix.argtypes = [_p, _p, _p]
 _lib.bip_reconstruct_local.argtypes = [_p, ctypes.c_int32, _p, _p, _p]
 _lib.bip_eels_signal.argtypes = [_p, ctypes.c_int32, _p, _p, _p, ctypes.c_int32, ctypes.c_int32,
@@ -59,9 +128,9 @@ _lib.bip_stage_timings.argtypes = [_p, _p, _p, ctypes.c_int32]
 _lib.bip_eels_backward.argtypes = [_p, ctypes.c_int32, _p, _p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, _p, _p, _p, _p, _p, _p, _p]
 _lib.bip_potential_build.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
-                                     _p, _p, _p, _p]
+                                     _p, _p, _p, _p, _p]
 _lib.bip_potential_grad.argtypes = [ctypes.POINTER(BipGrid), ctypes.c_int32, _p, ctypes.c_int32,
-                                    _p, _p, _p, _p, _p]
+                                    _p, _p, _p, _p, _p, _p]
 _lib.bip_plan_destroy.argtypes = [_p]
 _lib.bip_plan_destroy.restype = None
 _lib.bip_last_error.restype = ctypes.c_char_p
@@ -99,16 +168,19 @@ class Plan:
     """A bip_plan: geometry, parents, Sibson weights and device workspace."""
 
     def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
-                 win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None):
+                 win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None,
+                 allocator="torch", s2_window_gb=0.0):
         self._h = _p()
+        self._built_key = None
+        self.allocator, alloc_ref = _alloc_arg(allocator)
         grid = BipGrid(ny, nx, nz, ly, lx, dz)
         self.grid = grid
-        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride)
+        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride, s2_window_gb)
         tau, tp = _host(tau_xyz, np.float64)
         ws, wp = _host(win_size, np.int32)
         wo, op = _host(win_origin, np.int32)
         _check(_lib.bip_plan_create(ctypes.byref(grid), ctypes.byref(opt), int(tau.shape[0]), tp,
-                                    wp, op, _stream(stream), ctypes.byref(self._h)))
+                                    wp, op, alloc_ref, _stream(stream), ctypes.byref(self._h)))
         self.ny, self.nx, self.nz = ny, nx, nz
         self.win_size = ws.copy()
         c = self.query(Q_COUNTS)
@@ -135,7 +207,13 @@ class Plan:
     def build_smatrix(self, V, stream=None):
         """V: float32 device tensor [nz, ny, nx]."""
         assert V.is_contiguous() and V.dtype.itemsize == 4
+        self._built_key = None
         _check(_lib.bip_build_smatrix(self._h, _ptr(V), _stream(stream)))
+        self._built_key = _tensor_key(V)
+
+    def built_from(self, V):
+        """True when the last build_smatrix read this very tensor, unmodified."""
+        return self._built_key is not None and self._built_key == _tensor_key(V)
 
     def reconstruct_local(self, atom, s1_out=None, s2_out=None, stream=None):
         """s1_out: complex64 [B, W, W]; s2_out: complex64 [n_det, W, W] (device)."""
@@ -153,25 +231,23 @@ class Plan:
         else:
             sub, sp = _host(atom_subset, np.int32)
             ns = int(sub.size)
-        _check(_lib.bip_eels_signal(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]),
-                                    int(scan[1]), int(out_mode), int(precision), _ptr(out),
-                                    _stream(stream)))
+        fn = _lib.bip_eels_signal
+        _check(fn(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]), int(scan[1]), int(out_mode),
+                  int(precision), _ptr(out), _stream(stream)))
 
     def eels_backward(self, n_ch, H, H_off, scan, dL_dI, dL_dV, dL_dHconj=None, dHdx=None,
                       dHdy=None, want_tau=False, precision=PREC_FP32, stream=None):
-        """Gradient of a map loss (plan made with ckpt_stride=1, after build_smatrix).
+        """Gradient of a map loss (plan made with ckpt_stride >= 1, after build_smatrix).
         dL_dI: float32 device [P]; dL_dV: float32 device [nz, ny, nx] (written);
         dL_dHconj / dHdx / dHdy: complex64 device, ragged like H, or None;
         precision: PREC_FP32 or PREC_SPLIT_BF16 for the contraction products.
-        Returns dL/dtau_xy [n_atoms, 2] (float64) when want_tau, else None."""
+        Returns dL/dtau_xy [n_atoms, 2] (float64 device tensor) when want_tau, else None."""
         offs, op = _host(H_off, np.int64)
-        tau = np.zeros((self.n_atoms, 2), np.float64) if want_tau else None
+        tau = torch.empty((self.n_atoms, 2), dtype=torch.float64, device=dL_dV.device) \
+            if want_tau else None
         _check(_lib.bip_eels_backward(self._h, int(n_ch), _ptr(H), op, int(scan[0]), int(scan[1]),
                                       int(precision), _ptr(dL_dI), _ptr(dL_dV), _ptr(dL_dHconj),
-                                      _ptr(dHdx),
-                                      _ptr(dHdy),
-                                      tau.ctypes.data_as(ctypes.c_void_p) if want_tau else None,
-                                      _stream(stream)))
+                                      _ptr(dHdx), _ptr(dHdy), _ptr(tau), _stream(stream)))
         return tau
 
     def set_profiling(self, enable):
@@ -205,47 +281,61 @@ class Plan:
             return rp.copy(), col.copy(), w.copy()
         elif what == Q_SCALARS:
             buf = np.zeros(4, np.float64)
+        elif what == Q_MEMORY:
+            buf = np.zeros(3, np.int64)
         else:
             raise ValueError(what)
         _check(_lib.bip_query(self._h, what, buf.ctypes.data_as(ctypes.c_void_p)))
         return buf
 
 
-def potential_build(grid, xyz, amp, width, V, stream=None):
+def _tensor_key(t):
+    return (t.data_ptr(), t._version, tuple(t.shape), t.dtype)
+
+
+def potential_build(grid, xyz, amp, width, V, stream=None, allocator="torch"):
     """Slice potentials V (float32 device [nz, ny, nx]) from atom positions
     xyz [n, 3], amplitudes amp [n, K] and widths [K] (host arrays)."""
     x, xp = _host(xyz, np.float64)
     a, ap = _host(amp, np.float64)
     w, wp = _host(width, np.float64)
+    _, alloc_ref = _alloc_arg(allocator)
     _check(_lib.bip_potential_build(ctypes.byref(grid), int(x.shape[0]), xp, int(w.size), ap, wp,
-                                    _ptr(V), _stream(stream)))
+                                    _ptr(V), alloc_ref, _stream(stream)))
 
 
-def potential_grad(grid, xyz, amp, width, dL_dV, stream=None):
-    """dL/dxyz [n, 3] (float64, host) from dL/dV (float32 device)."""
+def potential_grad(grid, xyz, amp, width, dL_dV, out=None, stream=None, allocator="torch"):
+    """dL/dxyz [n, 3] (float64 device tensor, written into `out` when given)
+    from dL/dV (float32 device)."""
     x, xp = _host(xyz, np.float64)
     a, ap = _host(amp, np.float64)
     w, wp = _host(width, np.float64)
-    out = np.zeros((x.shape[0], 3), np.float64)
+    if out is None:
+        out = torch.empty((x.shape[0], 3), dtype=torch.float64, device=dL_dV.device)
+    assert out.is_contiguous() and out.dtype == torch.float64 and out.numel() == 3 * x.shape[0]
+    _, alloc_ref = _alloc_arg(allocator)
     _check(_lib.bip_potential_grad(ctypes.byref(grid), int(x.shape[0]), xp, int(w.size), ap, wp,
-                                   _ptr(dL_dV), out.ctypes.data_as(ctypes.c_void_p),
-                                   _stream(stream)))
+                                   _ptr(dL_dV), _ptr(out), alloc_ref, _stream(stream)))
     return out
 
 
 class EELSMap(torch.autograd.Function):
     """I = map(V, H) through bip_build_smatrix + bip_eels_signal; backward
-    through bip_eels_backward.  The plan must be made with ckpt_stride=1.
+    through bip_eels_backward.  The plan must be made with ckpt_stride >= 1.
     Gradients follow torch's complex convention (2 dL/d conj(H) for H)."""
 
     @staticmethod
     def forward(ctx, V, H, plan, n_ch, H_off, scan, precision):
+        if precision not in (PREC_FP32, PREC_SPLIT_BF16):
+            # the backward implements the FP32 and split products only; another
+            # forward precision would return the gradient of a different map
+            raise ValueError("EELSMap supports PREC_FP32 and PREC_SPLIT_BF16")
         P = int(scan[0]) * int(scan[1])
         out = torch.empty(P, dtype=torch.float32, device=V.device)
         plan.build_smatrix(V.contiguous())
         plan.eels_signal(n_ch, H.contiguous(), H_off, scan, OUT_MAP, precision, out)
         ctx.plan, ctx.n_ch, ctx.H_off, ctx.scan = plan, n_ch, H_off, scan
-        ctx.precision = PREC_FP32 if precision == PREC_FP32 else PREC_SPLIT_BF16
+        ctx.precision = precision
         ctx.save_for_backward(V, H)
         return out
 
@@ -254,8 +344,11 @@ class EELSMap(torch.autograd.Function):
         V, H = ctx.saved_tensors
         dV = torch.empty_like(V)
         gH = torch.empty_like(H) if ctx.needs_input_grad[1] else None
-        # the checkpoints belong to the last build: rebuild if another V was built since
-        ctx.plan.build_smatrix(V.contiguous())
+        # the checkpoints belong to the last build: rebuild only if another V
+        # (or this one, modified) was built since
+        Vc = V.contiguous()
+        if not ctx.plan.built_from(Vc):
+            ctx.plan.build_smatrix(Vc)
         ctx.plan.eels_backward(ctx.n_ch, H.contiguous(), ctx.H_off, ctx.scan,
                                grad_I.contiguous().float(), dV, dL_dHconj=gH,
                                precision=ctx.precision)
@@ -264,7 +357,8 @@ class EELSMap(torch.autograd.Function):
 
 class SlicePotential(torch.autograd.Function):
     """V = potential(xyz) through bip_potential_build; backward through
-    bip_potential_grad (host float64 positions, returned as a CPU tensor)."""
+    bip_potential_grad.  xyz: float64 tensor [n, 3] (any device; the library
+    reads the positions on the host); its gradient comes back on xyz's device."""
 
     @staticmethod
     def forward(ctx, xyz, grid, amp, width, shape):
@@ -272,12 +366,13 @@ class SlicePotential(torch.autograd.Function):
         x = xyz.detach().cpu().numpy()
         potential_build(grid, x, amp, width, V)
         ctx.grid, ctx.x, ctx.amp, ctx.width = grid, x, amp, width
+        ctx.xyz_device = xyz.device
         return V
 
     @staticmethod
     def backward(ctx, grad_V):
         g = potential_grad(ctx.grid, ctx.x, ctx.amp, ctx.width, grad_V.contiguous().float())
-        return torch.from_numpy(g), None, None, None, None
+        return g.to(ctx.xyz_device), None, None, None, None
 
 
 def library_path() -> str:

@@ -81,9 +81,16 @@ int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector
   int2* dslot = nullptr;
   double* dw = nullptr;
   void* tmp[3] = {nullptr, nullptr, nullptr};
-  HIPCHK(hipMalloc(&tmp[0], std::max<size_t>(1, query.size() * sizeof(int32_t))), "sibson alloc");
-  HIPCHK(hipMalloc(&tmp[1], std::max<size_t>(1, (size_t)nq * 16 * sizeof(int2))), "sibson alloc");
-  HIPCHK(hipMalloc(&tmp[2], std::max<size_t>(1, (size_t)nq * 16 * sizeof(double))), "sibson alloc");
+  const size_t tb[3] = {std::max<size_t>(4, query.size() * sizeof(int32_t)),
+                        std::max<size_t>(4, (size_t)nq * 16 * sizeof(int2)),
+                        std::max<size_t>(4, (size_t)nq * 16 * sizeof(double))};
+  for (int i = 0; i < 3; ++i) {
+    tmp[i] = raw_alloc(plan_alloc(p), tb[i], st);
+    if (!tmp[i]) {
+      for (int k = 0; k < i; ++k) raw_release(plan_alloc(p), tmp[k], tb[k], st);
+      return err(BIP_ENOMEM, "Sibson temporaries");
+    }
+  }
   dq = (int2*)tmp[0];
   dslot = (int2*)tmp[1];
   dw = (double*)tmp[2];
@@ -97,7 +104,7 @@ int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector
   if (e == hipSuccess)
     e = hipMemcpyAsync(sw.data(), dw, sw.size() * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  for (void* t : tmp) (void)hipFree(t);
+  for (int i = 0; i < 3; ++i) raw_release(plan_alloc(p), tmp[i], tb[i], st);
   if (e != hipSuccess) return hip_fail(e, "sibson weights");
   const double eps = 1e-12;
   std::map<std::pair<int, int>, int> index;
@@ -141,20 +148,21 @@ const char* bip_last_error(void) { return g_err.c_str(); }
 
 void bip_plan_destroy(bip_plan* p) {
   if (!p) return;
-  (void)hipDeviceSynchronize();
-  for (void* a : p->allocations) (void)hipFree(a);
+  (void)hipStreamSynchronize(p->stream);
+  for (auto& b : p->allocations) raw_release(plan_alloc(p), b.ptr, b.bytes, p->stream);
+  p->allocations.clear();
   for (auto& t : p->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
   }
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
-  if (p->d_work) (void)hipFree(p->d_work);
+  (void)hipStreamSynchronize(p->stream);  // stream-ordered releases complete before return
   delete p;
 }
 
 int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_atoms,
                     const double* tau_xyz, const int32_t* win_size, const int32_t* win_origin,
-                    void* stream, bip_plan** out) {
+                    const bip_alloc* alloc, void* stream, bip_plan** out) {
   if (!out) return err(BIP_EINVAL, "out is NULL");
   *out = nullptr;
   if (!grid || !optics || !tau_xyz || !win_size || !win_origin)
@@ -171,8 +179,8 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
     return err(BIP_EINVAL, "unknown recon_mode");
   if (o.ckpt_stride < 0) return err(BIP_EINVAL, "ckpt_stride must be >= 0");
-  if (o.ckpt_stride > 1)
-    return err(BIP_EUNSUPPORTED, "ckpt_stride above 1 (recomputed segments) is not implemented");
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return err(BIP_EINVAL, "bip_alloc needs both alloc and release");
   if (n_atoms < 1) return err(BIP_EINVAL, "n_atoms must be >= 1");
   for (int a = 0; a < n_atoms; ++a) {
     const int W = win_size[a];
@@ -187,6 +195,11 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   bip_plan* p = new bip_plan();
   p->g = g;
   p->o = o;
+  p->stream = st;
+  if (alloc) {
+    p->alloc = *alloc;
+    p->has_alloc = true;
+  }
   p->lambda = wavelength(o.energy_ev);
   p->sigma = interaction(o.energy_ev);
   p->L = std::max(g.ny, g.nx);
@@ -213,6 +226,16 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
   p->Bp1 = (int)p->par1.size() / 2;
   p->Bp2 = (int)p->par2.size() / 2;
+  // a parent past the signed index range would alias to another frequency of
+  // the grid (its plane wave and propagator phase would be the alias's)
+  for (const auto* par : {&p->par1, &p->par2})
+    for (size_t i = 0; i < par->size(); i += 2)
+      if ((*par)[i] < -g.ny / 2 || (*par)[i] >= g.ny / 2 || (*par)[i + 1] < -g.nx / 2 ||
+          (*par)[i + 1] >= g.nx / 2)
+        return fail(err(BIP_EUNSUPPORTED, "parent beam (" + std::to_string((*par)[i]) + ", " +
+                                              std::to_string((*par)[i + 1]) +
+                                              ") outside the grid's frequency range; use a "
+                                              "smaller aperture/detector or partition factor"));
   // atoms
   p->n_atoms = n_atoms;
   p->W.resize(n_atoms);
@@ -236,6 +259,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   }
   p->win1_elems = o1;
   p->win2_elems = o2;
+  p->seg_of.assign(n_atoms, 0);
   p->plane_start.assign(g.nz + 1, 0);
   for (int a = 0; a < n_atoms; ++a) p->plane_start[p->plane[a] + 1]++;
   for (int j = 0; j < g.nz; ++j) p->plane_start[j + 1] += p->plane_start[j];
@@ -246,9 +270,46 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   }
   p->i_min = *std::min_element(p->plane.begin(), p->plane.end());
   p->i_max = *std::max_element(p->plane.begin(), p->plane.end());
+  {
+    // S2 windows of all atoms above the budget: plane segments (from the exit
+    // down) whose windows fit it, one segment's block reused for the next
+    const double gb = o.s2_window_gb > 0 ? o.s2_window_gb : 48.0;
+    const int64_t budget = (int64_t)(gb * (double)(1ll << 30)) / 8;  // complex64 elements
+    if (p->win2_elems > budget) {
+      if (o.ckpt_stride != 0)
+        return fail(err(BIP_EUNSUPPORTED, "the S2 windows exceed s2_window_gb: streamed S2 has no "
+                                          "checkpoints for bip_eels_backward"));
+      p->s2_stream = true;
+      int64_t cur = 0, most = 0;
+      int hi = -1, lo = -1;
+      auto close = [&] {
+        p->seg_hi.push_back(hi);
+        p->seg_lo.push_back(lo);
+        most = std::max(most, cur);
+        cur = 0;
+        hi = -1;
+      };
+      for (int j = g.nz - 1; j >= 0; --j) {
+        int64_t pj = 0;
+        for (int q = p->plane_start[j]; q < p->plane_start[j + 1]; ++q)
+          pj += (int64_t)p->Bp2 * p->W[p->plane_atoms[q]] * p->W[p->plane_atoms[q]];
+        if (pj == 0) continue;
+        if (hi >= 0 && cur + pj > budget) close();
+        if (hi < 0) hi = j;
+        lo = j;
+        for (int q = p->plane_start[j]; q < p->plane_start[j + 1]; ++q) {
+          const int a = p->plane_atoms[q];
+          p->seg_of[a] = (int)p->seg_hi.size();
+          p->off2[a] = cur;
+          cur += (int64_t)p->Bp2 * p->W[a] * p->W[a];
+        }
+      }
+      close();
+      p->win2_elems = most;
+    }
+  }
   // device buffers
   const int64_t G = (int64_t)g.ny * g.nx;
-  std::vector<int2> tmp;
   auto as_int2 = [](const std::vector<int32_t>& v) {
     std::vector<int2> r(v.size() / 2);
     for (size_t i = 0; i < r.size(); ++i) r[i] = make_int2(v[2 * i], v[2 * i + 1]);
@@ -311,11 +372,14 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   tiles(p->rp2, ec2, ts2, tp2, el2);
   for (size_t t = 0; t + 1 < ts1.size(); ++t) p->tile_np1 = std::max(p->tile_np1, ts1[t + 1] - ts1[t]);
   for (size_t t = 0; t + 1 < ts2.size(); ++t) p->tile_np2 = std::max(p->tile_np2, ts2[t + 1] - ts2[t]);
-  if ((rc = dalloc(p, &p->d_tw, p->L)) || (rc = dalloc(p, &p->d_prop, G)) ||
-      (rc = dalloc(p, &p->d_T, G * g.nz)) || (rc = upload(p, &p->d_beams, as_int2(p->beams), st)) ||
-      (rc = upload(p, &p->d_det, as_int2(p->det), st)) ||
-      (rc = upload(p, &p->d_par1, as_int2(p->par1), st)) ||
-      (rc = upload(p, &p->d_par2, as_int2(p->par2), st)) ||
+  // host sources of the uploads live until the stream synchronization below
+  const std::vector<int2> beams2 = as_int2(p->beams), det2 = as_int2(p->det),
+                          par12 = as_int2(p->par1), par22 = as_int2(p->par2);
+  if ((rc = dalloc(p, &p->d_tw, p->L, st)) || (rc = dalloc(p, &p->d_prop, G, st)) ||
+      (rc = dalloc(p, &p->d_T, G * g.nz, st)) || (rc = upload(p, &p->d_beams, beams2, st)) ||
+      (rc = upload(p, &p->d_det, det2, st)) ||
+      (rc = upload(p, &p->d_par1, par12, st)) ||
+      (rc = upload(p, &p->d_par2, par22, st)) ||
       (rc = upload(p, &p->d_rp1, p->rp1, st)) || (rc = upload(p, &p->d_col1, p->col1, st)) ||
       (rc = upload(p, &p->d_w1, w1f, st)) || (rc = upload(p, &p->d_rp2, p->rp2, st)) ||
       (rc = upload(p, &p->d_col2, p->col2, st)) || (rc = upload(p, &p->d_w2, w2f, st)) ||
@@ -328,16 +392,20 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = upload(p, &p->d_ox, p->ox, st)) || (rc = upload(p, &p->d_off1, p->off1, st)) ||
       (rc = upload(p, &p->d_off2, p->off2, st)) ||
       (rc = upload(p, &p->d_grec1, grec1, st)) || (rc = upload(p, &p->d_grec2, grec2, st)) ||
-      (rc = dalloc(p, &p->d_state1, (size_t)p->Bp1 * G)) ||
-      (rc = dalloc(p, &p->d_state2, (size_t)p->Bp2 * G)) ||
-      (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems)) ||
-      (rc = dalloc(p, &p->d_win2, (size_t)p->win2_elems)))
+      (rc = dalloc(p, &p->d_state1, (size_t)p->Bp1 * G, st)) ||
+      (rc = dalloc(p, &p->d_state2, (size_t)p->Bp2 * G, st)) ||
+      (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems, st)) ||
+      (rc = dalloc(p, &p->d_win2, (size_t)p->win2_elems, st)))
     return fail(rc);
-  if (o.ckpt_stride == 1) {
-    const size_t n1 = (size_t)p->i_max * p->Bp1 * G, n2 = (size_t)(g.nz - p->i_min) * p->Bp2 * G;
-    if ((rc = dalloc(p, &p->d_prop_conj, G)) || (n1 && (rc = dalloc(p, &p->d_ckpt1, n1))) ||
-        (rc = dalloc(p, &p->d_ckpt2, n2)) || (rc = dalloc(p, &p->d_gwin1, (size_t)p->win1_elems)) ||
-        (rc = dalloc(p, &p->d_gwin2, (size_t)p->win2_elems)))
+  if (o.ckpt_stride >= 1) {
+    // one checkpoint per segment of ckpt_stride slices: S1 slices 0 .. i_max-1
+    // in segments [mK, mK + K), S2 slices nz-1 .. i_min in segments from the exit
+    const int K = o.ckpt_stride;
+    const size_t n1 = (size_t)((p->i_max + K - 1) / K) * p->Bp1 * G,
+                 n2 = (size_t)((g.nz - p->i_min + K - 1) / K) * p->Bp2 * G;
+    if ((rc = dalloc(p, &p->d_prop_conj, G, st)) || (n1 && (rc = dalloc(p, &p->d_ckpt1, n1, st))) ||
+        (rc = dalloc(p, &p->d_ckpt2, n2, st)) || (rc = dalloc(p, &p->d_gwin1, (size_t)p->win1_elems, st)) ||
+        (rc = dalloc(p, &p->d_gwin2, (size_t)p->win2_elems, st)))
       return fail(rc);
   }
   hipError_t e = launch_twiddles(p->d_tw, p->L, st);
@@ -354,6 +422,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
 int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   if (!p || !V) return err(BIP_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
   HIPCHK(timed(p, ST_TRANSMIT, st, [&] { return launch_transmit(p->d_T, V, G * g.nz, (float)p->sigma, st); }), "transmit");
@@ -366,7 +435,7 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
   HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves(p->d_state1, p->d_par1, p->Bp1, g.ny, g.nx, p->d_tw, p->L, +1, 1.0f, st); }),
          "init S1");
   GatherArgs g1 = gather_args(p, 1);
-  const int batch1 = balanced_batch(p->Bp1, batch), batch2 = balanced_batch(p->Bp2, batch);
+  const int batch1 = balanced_batch(p->Bp1, batch);
   for (int c0 = 0; c0 < p->Bp1; c0 += batch1) {
     const int nc = std::min(batch1, p->Bp1 - c0);
     float2* s1 = p->d_state1 + (int64_t)c0 * G;
@@ -375,9 +444,9 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
       if (j > 0) flags |= ROW_INV;
       if (j < p->i_max) flags |= ROW_T | ROW_FWD;
       float2* save = nullptr;
-      if (p->d_ckpt1 && j < p->i_max) {
+      if (p->d_ckpt1 && j < p->i_max && j % p->o.ckpt_stride == 0) {
         flags |= ROW_SAVE;
-        save = p->d_ckpt1 + ((int64_t)j * p->Bp1 + c0) * G;
+        save = p->d_ckpt1 + ((int64_t)(j / p->o.ckpt_stride) * p->Bp1 + c0) * G;
       }
       HIPCHK(timed(p, ST_S1_ROW, st, [&] { return launch_row_pass(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
                              p->d_par1, +1, g1, p->plane_start[j], p->plane_start[j + 1], c0, save, st); }),
@@ -387,39 +456,60 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
                "S1 column pass");
     }
   }
-  // ---- S2: exit -> shallowest ionization plane (transpose multislice).  The
-  // parents start row-transformed, the form the state keeps between passes.
-  HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves_rowft(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw,
-                                p->L, (float)(1.0 / std::sqrt((double)G)), st); }),
-         "init S2");
+  // ---- S2: exit -> shallowest ionization plane (transpose multislice);
+  // streamed plans sweep S2 inside bip_eels_signal, segment by segment
+  if (!p->s2_stream) {
+    int rc = sweep_s2(p, g.nz - 1, p->i_min, true, st);
+    if (rc) return rc;
+  }
+  p->built = true;
+  return BIP_OK;
+}
+
+}  // extern "C"
+
+int bip::sweep_s2(bip_plan* p, int j_hi, int j_lo, bool init, hipStream_t st) {
+  const bip_grid& g = p->g;
+  const int64_t G = (int64_t)g.ny * g.nx;
+  const int batch = column_batch(G);
+  p->column_batch = batch;
+  const int batch2 = balanced_batch(p->Bp2, batch);
+  // The parents start row-transformed, the form the state keeps between passes.
+  if (init)
+    HIPCHK(timed(p, ST_INIT, st, [&] { return launch_init_planewaves_rowft(p->d_state2, p->d_par2, p->Bp2, g.ny, g.nx, p->d_tw,
+                                  p->L, (float)(1.0 / std::sqrt((double)G)), st); }),
+           "init S2");
   GatherArgs g2 = gather_args(p, 2);
   for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
     const int nc = std::min(batch2, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
-    for (int j = g.nz - 1; j >= p->i_min; --j) {
+    for (int j = j_hi; j >= j_lo; --j) {
       HIPCHK(timed(p, ST_S2_COL, st, [&] { return launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st); }),
              "S2 column pass");
       int flags = ROW_INV | ROW_T | ROW_GATHER_AFTER_T;
-      if (j > p->i_min) flags |= ROW_FWD;
+      if (j > p->i_min) flags |= ROW_FWD;  // keep the state row-transformed until the last plane
       float2* save = nullptr;
-      if (p->d_ckpt2) {
+      if (p->d_ckpt2 && (g.nz - 1 - j) % p->o.ckpt_stride == 0) {
         flags |= ROW_SAVE;
-        save = p->d_ckpt2 + ((int64_t)(j - p->i_min) * p->Bp2 + c0) * G;
+        save = p->d_ckpt2 + ((int64_t)((g.nz - 1 - j) / p->o.ckpt_stride) * p->Bp2 + c0) * G;
       }
       HIPCHK(timed(p, ST_S2_ROW, st, [&] { return launch_row_pass(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L,
                              p->d_par2, -1, g2, p->plane_start[j], p->plane_start[j + 1], c0, save, st); }),
              "S2 row pass");
     }
   }
-  p->built = true;
   return BIP_OK;
 }
+
+extern "C" {
 
 int bip_parent_windows(bip_plan* p, int32_t atom, int32_t which, float* out, void* stream) {
   if (!p || !out) return err(BIP_EINVAL, "NULL argument");
   if (atom < 0 || atom >= p->n_atoms) return err(BIP_EINVAL, "atom out of range");
   if (which != 1 && which != 2) return err(BIP_EINVAL, "which must be 1 or 2");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
+  if (which == 2 && p->s2_stream)
+    return err(BIP_EUNSUPPORTED, "S2 windows of this plan are streamed inside bip_eels_signal");
   const int W = p->W[atom];
   const size_t n = (size_t)(which == 1 ? p->Bp1 : p->Bp2) * W * W;
   const float2* src = which == 1 ? p->d_win1 + p->off1[atom] : p->d_win2 + p->off2[atom];
@@ -433,6 +523,8 @@ int bip_reconstruct_local(bip_plan* p, int32_t atom, float* s1_out, float* s2_ou
   if (atom < 0 || atom >= p->n_atoms) return err(BIP_EINVAL, "atom out of range");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   hipStream_t st = (hipStream_t)stream;
+  if (s2_out && p->s2_stream)
+    return err(BIP_EUNSUPPORTED, "S2 windows of this plan are streamed inside bip_eels_signal");
   if (s1_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 1), (float2*)s1_out, st), "recon S1");
   if (s2_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 2), (float2*)s2_out, st), "recon S2");
   return BIP_OK;
@@ -442,6 +534,24 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
                     const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
                     int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
                     void* stream) {
+  return bip::eels_signal_impl(p, n_ch, H, H_off, atom_subset, n_subset, scan_sy, scan_sx, out_mode,
+                               precision, out, nullptr, 0, stream);
+}
+
+}  // extern "C"
+
+static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t n_ch, const float* H,
+                        const int64_t* H_off, int32_t scan_sy, int32_t scan_sx, int32_t out_mode,
+                        int32_t precision, float* out, void* ext_work, size_t ext_bytes,
+                        bool accumulate, hipStream_t st);
+
+// Steps (b) + (c).  With `ext_work` the workspace is that caller-given device
+// block of `ext_bytes` (nothing is allocated); else the plan's own workspace,
+// grown on demand.
+int bip::eels_signal_impl(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
+                          const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
+                          int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
+                          void* ext_work, size_t ext_bytes, void* stream) {
   if (!p || !H || !H_off || !out) return err(BIP_EINVAL, "NULL argument");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
@@ -469,6 +579,41 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     for (int a = 0; a < p->n_atoms; ++a) atoms.push_back(a);
   }
   hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
+  if (!p->s2_stream)
+    return signal_atoms(p, atoms, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
+                        ext_bytes, false, st);
+  // S2 streamed: sweep a plane segment, contract its atoms (in the listed
+  // order), then the next segment; the outputs accumulate over the segments
+  int last = -1;
+  for (int a : atoms) last = std::max(last, p->seg_of[a]);
+  int calls = 0;
+  for (int k = 0; k <= last; ++k) {
+    const int j_from = k == 0 ? p->g.nz - 1 : p->seg_lo[k - 1] - 1;
+    int rc = sweep_s2(p, j_from, p->seg_lo[k], k == 0, st);
+    if (rc) return rc;
+    std::vector<int32_t> seg;
+    for (int a : atoms)
+      if (p->seg_of[a] == k) seg.push_back(a);
+    if (seg.empty()) continue;
+    rc = signal_atoms(p, seg, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
+                      ext_bytes, calls > 0, st);
+    if (rc) return rc;
+    ++calls;
+  }
+  if (calls == 0)  // no atom selected: the outputs are zero
+    return signal_atoms(p, {}, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
+                        ext_bytes, false, st);
+  return BIP_OK;
+}
+
+// Reconstruction and contraction of `atoms` (whose S2 windows are in the
+// plan's window stack); accumulate: add to the outputs instead of
+// overwriting them.
+static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t n_ch, const float* H,
+                        const int64_t* H_off, int32_t scan_sy, int32_t scan_sx, int32_t out_mode,
+                        int32_t precision, float* out, void* ext_work, size_t ext_bytes,
+                        bool accumulate, hipStream_t st) {
   const bool gram = out_mode == BIP_OUT_MAP;          // map via psi^H Q psi
   const bool map_direct = out_mode == BIP_OUT_MAP_DIRECT;
   const int P = scan_sy * scan_sx;
@@ -533,7 +678,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   }
   const char* env = std::getenv("BIP_WORKSPACE_GB");
   const double budget_gb = env ? std::atof(env) : 24.0;
-  const int64_t budget = (int64_t)(budget_gb * (1 << 30));
+  const int64_t budget = ext_work ? (int64_t)ext_bytes - 16 * 256 : (int64_t)(budget_gb * (1 << 30));
   const int64_t n_jobs_total = (int64_t)atoms.size() * (n_ch + 2);
   const int64_t fixed = n_partial_tiles * Ppad * 4 +
                         (out_mode == BIP_OUT_QEELS ? (int64_t)P * p->ndet * 4 : 0) +
@@ -557,9 +702,23 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
       b = e;
     }
   }
-  int rc = ensure_work(p, (size_t)(fixed + max_chunk + 16 * 256));
-  if (rc) return rc;
-  Workspace ws{(char*)p->d_work, 0};
+  const size_t need = (size_t)(fixed + max_chunk + 16 * 256);
+  char* work_base = nullptr;
+  size_t work_cap = 0;
+  if (ext_work) {
+    if (need > ext_bytes)
+      return err(BIP_EUNSUPPORTED, "this signal needs " + std::to_string(need) +
+                                       " bytes of workspace; the allocation-free entry point has " +
+                                       std::to_string(ext_bytes));
+    work_base = (char*)ext_work;
+    work_cap = ext_bytes;
+  } else {
+    int rc = ensure_work(p, need, st);
+    if (rc) return rc;
+    work_base = (char*)p->d_work;
+    work_cap = p->work_bytes;
+  }
+  Workspace ws{work_base, 0};
   float* partial = (float*)ws.take(n_partial_tiles * Ppad * 4);
   float* beams_out = out_mode == BIP_OUT_BEAMS ? out : nullptr;
   float* beams_tmp = nullptr;
@@ -573,11 +732,11 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
   float2* d_tws = (float2*)ws.take(tws.size() * 8);
   ReconAtom* d_ratoms = (ReconAtom*)ws.take(atoms.size() * sizeof(ReconAtom));
   const size_t chunk_base = ws.used;
-  if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: tables exceed the workspace");
+  if (ws.used > work_cap) return err(BIP_ENOMEM, "internal: tables exceed the workspace");
   HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
   HIPCHK(hipMemcpyAsync(d_tws, tws.data(), tws.size() * 8, hipMemcpyHostToDevice, st), "twiddles");
-  if (out_mode == BIP_OUT_MAP || map_direct) HIPCHK(launch_zero(out, P, st), "zero");
-  if (beams_out) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
+  if ((out_mode == BIP_OUT_MAP || map_direct) && !accumulate) HIPCHK(launch_zero(out, P, st), "zero");
+  if (beams_out && (beams_tmp || !accumulate)) HIPCHK(launch_zero(beams_out, (int64_t)P * p->ndet, st), "zero");
   // job tables, chunk-relative offsets
   std::vector<ProbeJob>& jprobe = p->h_probe;
   std::vector<GemmJob>& jdet = p->h_jobs2;
@@ -703,7 +862,7 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     char* S2op = (char*)ws.take(pl1 * csz);
     char* X2 = (char*)ws.take(pl2 * csz);   // Q (Gram) or U (direct)
     char* PsiT = (char*)ws.take(std::max<int64_t>(pl3, 1) * csz);
-    if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
+    if (ws.used > work_cap) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
     int max_n1 = 0, max_w2 = 0, max_kd = 0;
     const int c0 = chunks[c].first, c1 = chunks[c].second, nat = c1 - c0;
     for (int i = c0; i < c1; ++i) {
@@ -831,13 +990,16 @@ int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_
     }
     int32_t* d_start = (int32_t*)ws.take(start.size() * 4);
     int32_t* d_list = (int32_t*)ws.take(list.size() * 4 + 4);
-    if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "qEELS bin tables exceed the workspace");
+    if (ws.used > work_cap) return err(BIP_ENOMEM, "qEELS bin tables exceed the workspace");
     HIPCHK(hipMemcpyAsync(d_start, start.data(), start.size() * 4, hipMemcpyHostToDevice, st), "bins");
     HIPCHK(hipMemcpyAsync(d_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st), "bins");
-    HIPCHK(launch_qeels_from_beams(beams_tmp, d_start, d_list, p->ndet, P, p->nq, out, st), "qeels");
+    HIPCHK(launch_qeels_from_beams(beams_tmp, d_start, d_list, p->ndet, P, p->nq, out, accumulate ? 1 : 0, st),
+           "qeels");
   }
   return BIP_OK;
 }
+
+extern "C" {
 
 int bip_set_profiling(bip_plan* p, int32_t enable) {
   if (!p) return err(BIP_EINVAL, "NULL plan");
@@ -894,12 +1056,19 @@ int bip_query(const bip_plan* p, int32_t what, void* out) {
       std::memcpy(o, w.data(), w.size() * 8);
       return BIP_OK;
     }
+    case BIP_Q_MEMORY: {
+      int64_t* o = (int64_t*)out;
+      o[0] = p->bytes_now;
+      o[1] = p->bytes_peak;
+      o[2] = (int64_t)p->allocations.size();
+      return BIP_OK;
+    }
     case BIP_Q_SCALARS: {
       double* o = (double*)out;
       o[0] = p->lambda;
       o[1] = p->sigma;
       o[2] = p->column_batch;
-      o[3] = 0;
+      o[3] = p->s2_stream ? (double)p->seg_hi.size() : 0.0;
       return BIP_OK;
     }
     default:

@@ -4,7 +4,8 @@
 // The backward recomputes, atom by atom, what the forward contraction used
 // (psi, S2~, the Gram matrix) in FP32, forms the cotangents of the parent
 // windows, then runs the two parent sweeps in reverse with the slice
-// checkpoints kept by bip_build_smatrix (ckpt_stride = 1), injecting the
+// checkpoints kept by bip_build_smatrix (every ckpt_stride-th slice; the slices
+// between two checkpoints are recomputed per column batch), injecting the
 // window cotangents at their planes and reducing dL/dV in a fixed order.
 #include <hip/hip_runtime.h>
 
@@ -68,6 +69,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
       return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
   hipStream_t st = (hipStream_t)stream;
+  p->stream = st;
   const bip_grid& g = p->g;
   const int64_t G = (int64_t)g.ny * g.nx;
   const int P = scan_sy * scan_sx;
@@ -124,18 +126,16 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   }
   // transposed weights (parent -> beams), built once per plan
   if (!p->d_tp1_rp) {
-    std::vector<int32_t> rp, tb;
-    std::vector<float> tw;
+    std::vector<int32_t> rp1, tb1, rp2, tb2;
+    std::vector<float> tw1, tw2;
     int rc;
-    transpose_csr(p->rp1, p->col1, p->w1, p->Bp1, rp, tb, tw);
-    if ((rc = upload(p, &p->d_tp1_rp, rp, st)) || (rc = upload(p, &p->d_tp1_b, tb, st)) ||
-        (rc = upload(p, &p->d_tp1_w, tw, st)))
+    transpose_csr(p->rp1, p->col1, p->w1, p->Bp1, rp1, tb1, tw1);
+    transpose_csr(p->rp2, p->col2, p->w2, p->Bp2, rp2, tb2, tw2);
+    if ((rc = upload(p, &p->d_tp1_rp, rp1, st)) || (rc = upload(p, &p->d_tp1_b, tb1, st)) ||
+        (rc = upload(p, &p->d_tp1_w, tw1, st)) || (rc = upload(p, &p->d_tp2_rp, rp2, st)) ||
+        (rc = upload(p, &p->d_tp2_b, tb2, st)) || (rc = upload(p, &p->d_tp2_w, tw2, st)))
       return rc;
-    transpose_csr(p->rp2, p->col2, p->w2, p->Bp2, rp, tb, tw);
-    if ((rc = upload(p, &p->d_tp2_rp, rp, st)) || (rc = upload(p, &p->d_tp2_b, tb, st)) ||
-        (rc = upload(p, &p->d_tp2_w, tw, st)))
-      return rc;
-    HIPCHK(hipStreamSynchronize(st), "weight tables");  // the host vectors go out of scope
+    HIPCHK(hipStreamSynchronize(st), "weight tables");  // once per plan: the host vectors go out of scope
   }
   // Workspace.  The products of the contraction backward run batched over
   // chunks of atoms (one launch per product and chunk, grid z or the Gram job
@@ -166,12 +166,17 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   sz(tws.size() * 8);
   sz(jprobe.size() * sizeof(ProbeJob));
   sz(4 * (size_t)p->n_atoms * sizeof(GemmJob));
+  // checkpoint segments longer than one slice are recomputed per column batch:
+  // a forward state [batch][G] and the K - 1 recomputed slices [K - 1][batch][G]
+  const int K = p->o.ckpt_stride;
+  const int bmax = std::max(balanced_batch(p->Bp1, batch), balanced_batch(p->Bp2, batch));
+  if (K > 1) sz((size_t)K * bmax * G * 8);
   const char* env = std::getenv("BIP_WORKSPACE_GB");
   const double budget_gb = env ? std::atof(env) : 24.0;
   const int64_t budget = (int64_t)(budget_gb * (1 << 30));
   const int nat_max =
       (int)std::max<int64_t>(1, std::min<int64_t>(p->n_atoms, (budget - (int64_t)fixed) / per_atom));
-  int rc = ensure_work(p, fixed + (size_t)nat_max * per_atom + 4096);
+  int rc = ensure_work(p, fixed + (size_t)nat_max * per_atom + 4096, st);
   if (rc) return rc;
   Workspace ws{(char*)p->d_work, 0};
   float2* Z = (float2*)ws.take((size_t)bX * 8);
@@ -200,6 +205,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   char* Kp = (char*)ws.take((size_t)(2 * NA * bQ) * 4);
   float2* gpsi = (float2*)ws.take((size_t)(NA * bGp) * 8);
   float2* gS2 = (float2*)ws.take((size_t)(NA * bGs) * 8);
+  float2* rec = K > 1 ? (float2*)ws.take((size_t)K * bmax * G * 8) : nullptr;
   if (ws.used > p->work_bytes) return err(BIP_ENOMEM, "internal: backward workspace");
   // the atom's slot in its chunk (chunks are consecutive runs of nat_max atoms)
   for (int a = 0; a < p->n_atoms; ++a) {
@@ -401,6 +407,26 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   const float two_sigma = (float)(2.0 * p->sigma);
   GatherArgs inj1{p->d_grec1, p->d_gwin1}, inj2{p->d_grec2, p->d_gwin2};
   auto ps = [&](int j) { return p->plane_start[j]; };
+  // The state after T_j of slice j: the checkpoint itself at a segment start,
+  // else recomputed for the batch.  recompute() advances a copy of a segment's
+  // checkpoint through the later slices of the segment, keeping each one.
+  auto seg_slot = [&](int r) { return rec + (int64_t)(1 + r) * bmax * G; };
+  auto recompute = [&](const float2* ck, int nc, int n_more, auto slice_of, const int2* par) -> int {
+    if (n_more <= 0) return BIP_OK;
+    HIPCHK(hipMemcpyAsync(rec, ck, (size_t)nc * G * 8, hipMemcpyDeviceToDevice, st), "segment copy");
+    GatherArgs none{nullptr, nullptr};
+    HIPCHK(launch_row_pass(ROW_FWD, rec, nc, g.ny, g.nx, nullptr, p->d_tw, p->L, par, 0, none, 0, 0, 0,
+                           nullptr, st),
+           "segment row transform");
+    for (int r = 0; r < n_more; ++r) {
+      const int j = slice_of(r);
+      HIPCHK(launch_col_pass(rec, nc, g.ny, g.nx, p->d_prop, p->d_tw, p->L, st), "segment column pass");
+      HIPCHK(launch_row_pass(ROW_INV | ROW_T | ROW_FWD | ROW_SAVE, rec, nc, g.ny, g.nx, p->d_T + j * G,
+                             p->d_tw, p->L, par, 0, none, 0, 0, 0, seg_slot(r), st),
+             "segment row pass");
+    }
+    return BIP_OK;
+  };
   // S1: psi_{j+1} = P(T_j psi_j); windows of plane j come from psi_j
   if (p->i_max > 0) {
     const int batch1 = balanced_batch(p->Bp1, batch);
@@ -412,53 +438,76 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
       HIPCHK(launch_row_adjoint(ADJ_ZERO | ADJ_INJ_AFTER | ADJ_FWD, s1, nc, g.ny, g.nx, nullptr,
                                 p->d_tw, p->L, inj1, ps(i), ps(i + 1), c0, nullptr, 0.f, nullptr, grp, st),
              "S1 adjoint start");
-      for (int j = p->i_max - 1; j >= 0; --j) {
-        HIPCHK(launch_col_pass(s1, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S1 adjoint column pass");
-        int flags = ADJ_INV | ADJ_DV;
-        if (j > 0) flags |= ADJ_CONJT | ADJ_INJ_AFTER | ADJ_FWD;
-        HIPCHK(launch_row_adjoint(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj1,
-                                  ps(j), ps(j + 1), c0, p->d_ckpt1 + ((int64_t)j * p->Bp1 + c0) * G,
-                                  two_sigma, dvp, grp, st),
-               "S1 adjoint row pass");
-        HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+      for (int m = (p->i_max - 1) / K; m >= 0; --m) {
+        const int js = m * K, je = std::min(js + K, p->i_max) - 1;  // slices js .. je
+        const float2* ck = p->d_ckpt1 + ((int64_t)m * p->Bp1 + c0) * G;
+        int rc = recompute(ck, nc, je - js, [&](int r) { return js + 1 + r; }, p->d_par1 + c0);
+        if (rc) return rc;
+        for (int j = je; j >= js; --j) {
+          const float2* u = j == js ? ck : seg_slot(j - js - 1);
+          HIPCHK(launch_col_pass(s1, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S1 adjoint column pass");
+          int flags = ADJ_INV | ADJ_DV;
+          if (j > 0) flags |= ADJ_CONJT | ADJ_INJ_AFTER | ADJ_FWD;
+          HIPCHK(launch_row_adjoint(flags, s1, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj1,
+                                    ps(j), ps(j + 1), c0, u, two_sigma, dvp, grp, st),
+                 "S1 adjoint row pass");
+          HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+        }
       }
     }
   }
-  // S2: v_j = T_j P v_{j+1}; windows of plane j come from v_j
+  // S2: v_j = T_j P v_{j+1}; windows of plane j come from v_j.  Segments from
+  // the exit: m covers slices nz-1-mK down to nz-K-mK (and not below i_min).
   const int batch2 = balanced_batch(p->Bp2, batch);
+  const int nseg2 = (g.nz - p->i_min + K - 1) / K;
   for (int c0 = 0; c0 < p->Bp2; c0 += batch2) {
     const int nc = std::min(batch2, p->Bp2 - c0);
     float2* s2 = p->d_state2 + (int64_t)c0 * G;
     const int grp = std::min(groups, nc);
-    for (int j = p->i_min; j < g.nz; ++j) {
-      int flags = ADJ_INJ_BEFORE | ADJ_DV;
-      flags |= j == p->i_min ? ADJ_ZERO : ADJ_INV;
-      if (j < g.nz - 1) flags |= ADJ_CONJT | ADJ_FWD;
-      if (j > p->i_min)
-        HIPCHK(launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S2 adjoint column pass");
-      HIPCHK(launch_row_adjoint(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj2, ps(j),
-                                ps(j + 1), c0, p->d_ckpt2 + ((int64_t)(j - p->i_min) * p->Bp2 + c0) * G,
-                                two_sigma, dvp, grp, st),
-             "S2 adjoint row pass");
-      HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+    for (int m = nseg2 - 1; m >= 0; --m) {
+      const int jh = g.nz - 1 - m * K, jl = std::max(p->i_min, jh - K + 1);  // slices jh .. jl
+      const float2* ck = p->d_ckpt2 + ((int64_t)m * p->Bp2 + c0) * G;
+      int rc = recompute(ck, nc, jh - jl, [&](int r) { return jh - 1 - r; }, p->d_par2 + c0);
+      if (rc) return rc;
+      for (int j = jl; j <= jh; ++j) {
+        const float2* v = j == jh ? ck : seg_slot(jh - 1 - j);
+        int flags = ADJ_INJ_BEFORE | ADJ_DV;
+        flags |= j == p->i_min ? ADJ_ZERO : ADJ_INV;
+        if (j < g.nz - 1) flags |= ADJ_CONJT | ADJ_FWD;
+        if (j > p->i_min)
+          HIPCHK(launch_col_pass(s2, nc, g.ny, g.nx, p->d_prop_conj, p->d_tw, p->L, st), "S2 adjoint column pass");
+        HIPCHK(launch_row_adjoint(flags, s2, nc, g.ny, g.nx, p->d_T + j * G, p->d_tw, p->L, inj2, ps(j),
+                                  ps(j + 1), c0, v, two_sigma, dvp, grp, st),
+               "S2 adjoint row pass");
+        HIPCHK(launch_dv_reduce(dvp, grp, G, dL_dV + j * G, st), "dV reduce");
+      }
     }
   }
-  if (dL_dtau_xy) {
-    HIPCHK(hipMemcpyAsync(dL_dtau_xy, dtau, (size_t)p->n_atoms * 16, hipMemcpyDeviceToHost, st), "dtau");
-    HIPCHK(hipStreamSynchronize(st), "dtau");
-  }
+  if (dL_dtau_xy)
+    HIPCHK(hipMemcpyAsync(dL_dtau_xy, dtau, (size_t)p->n_atoms * 16, hipMemcpyDeviceToDevice, st), "dtau");
   return BIP_OK;
 }
-
-int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
-                        const double* amp, const double* width, float* V, void* stream);
-int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
-                       const double* amp, const double* width, const float* dL_dV,
-                       double* dL_dxyz, void* stream);
 
 }  // extern "C"
 
 namespace {
+
+// Device temporaries of the potential helpers, released in stream order.
+struct Temps {
+  const bip_alloc* al;
+  hipStream_t st;
+  std::vector<std::pair<void*, size_t>> blocks;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void* p = raw_alloc(al, bytes, st);
+    if (p) blocks.push_back({p, bytes});
+    return (T*)p;
+  }
+  ~Temps() {
+    for (auto& b : blocks) raw_release(al, b.first, b.second, st);
+  }
+};
 
 // Terms (x, y, A, w) of every (atom, Gaussian) grouped by slice.
 int slice_terms(const bip_grid& g, int n_atoms, const double* xyz, int n_terms, const double* amp,
@@ -495,8 +544,10 @@ int slice_terms(const bip_grid& g, int n_atoms, const double* xyz, int n_terms, 
 extern "C" {
 
 int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
-                        const double* amp, const double* width, float* V, void* stream) {
+                        const double* amp, const double* width, float* V, const bip_alloc* alloc,
+                        void* stream) {
   if (!grid || !V || (n_atoms > 0 && (!xyz || !amp)) || !width) return err(BIP_EINVAL, "NULL argument");
+  if (alloc && (!alloc->alloc || !alloc->release)) return err(BIP_EINVAL, "bip_alloc needs both callbacks");
   const bip_grid g = *grid;
   std::vector<double> terms;
   std::vector<int64_t> start;
@@ -505,29 +556,27 @@ int bip_potential_build(const bip_grid* grid, int32_t n_atoms, const double* xyz
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   const int64_t nt_all = (int64_t)owner.size();
-  double *d_terms = nullptr, *d_prof = nullptr;
-  int64_t* d_start = nullptr;
-  hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_prof, (size_t)std::max<int64_t>(nt_all, 1) * (g.ny + g.nx) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_start, start.size() * 8);
-  if (e == hipSuccess && !terms.empty())
-    e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 0, d_prof, nullptr, st);
-  if (e == hipSuccess) e = launch_build_slices(d_terms, d_prof, d_start, g.nz, g.ny, g.nx, V, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(d_terms);
-  (void)hipFree(d_prof);
-  (void)hipFree(d_start);
-  if (e != hipSuccess) return hip_fail(e, "potential build");
+  Temps tmp{alloc, st, {}};
+  double* d_terms = tmp.take<double>(terms.size());
+  double* d_prof = tmp.take<double>((size_t)nt_all * (g.ny + g.nx));
+  int64_t* d_start = tmp.take<int64_t>(start.size());
+  if (!d_terms || !d_prof || !d_start) return err(BIP_ENOMEM, "potential build temporaries");
+  // pageable host sources: HIP copies them synchronously, so the vectors may
+  // go out of scope when the calls return
+  if (!terms.empty())
+    HIPCHK(hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st), "terms");
+  HIPCHK(hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st), "terms");
+  HIPCHK(launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 0, d_prof, nullptr, st), "profiles");
+  HIPCHK(launch_build_slices(d_terms, d_prof, d_start, g.nz, g.ny, g.nx, V, st), "potential build");
   return BIP_OK;
 }
 
 int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz, int32_t n_terms,
                        const double* amp, const double* width, const float* dL_dV,
-                       double* dL_dxyz, void* stream) {
+                       double* dL_dxyz, const bip_alloc* alloc, void* stream) {
   if (!grid || !dL_dV || !dL_dxyz || (n_atoms > 0 && (!xyz || !amp)) || !width)
     return err(BIP_EINVAL, "NULL argument");
+  if (alloc && (!alloc->alloc || !alloc->release)) return err(BIP_EINVAL, "bip_alloc needs both callbacks");
   const bip_grid g = *grid;
   std::vector<double> terms;
   std::vector<int64_t> start;
@@ -538,38 +587,28 @@ int bip_potential_grad(const bip_grid* grid, int32_t n_atoms, const double* xyz,
   int64_t most = 1;
   for (int j = 0; j < g.nz; ++j) most = std::max(most, start[j + 1] - start[j]);
   const int64_t nt_all = (int64_t)owner.size();
-  double *d_terms = nullptr, *d_prof = nullptr, *d_dprof = nullptr, *d_out = nullptr, *d_part = nullptr;
-  int64_t* d_start = nullptr;
-  const size_t prof_bytes = (size_t)std::max<int64_t>(nt_all, 1) * (g.ny + g.nx) * 8;
-  hipError_t e = hipMalloc(&d_terms, std::max<size_t>(terms.size(), 4) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_prof, prof_bytes);
-  if (e == hipSuccess) e = hipMalloc(&d_dprof, prof_bytes);
-  if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)std::max<int64_t>(nt_all, 1) * 16);
-  if (e == hipSuccess) e = hipMalloc(&d_part, (size_t)std::max<int64_t>(grad_part_doubles(nt_all, g.ny), 1) * 8);
-  if (e == hipSuccess) e = hipMalloc(&d_start, start.size() * 8);
-  if (e == hipSuccess && !terms.empty())
-    e = hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 1, d_prof, d_dprof, st);
-  if (e == hipSuccess)
-    e = launch_grad_terms(d_terms, d_prof, d_dprof, d_start, nt_all, (int)most, g.nz, g.ny, g.nx, dL_dV,
-                          d_part, d_out, st);
-  std::vector<double> out(2 * (size_t)nt_all);
-  if (e == hipSuccess && nt_all)
-    e = hipMemcpyAsync(out.data(), d_out, out.size() * 8, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(d_terms);
-  (void)hipFree(d_prof);
-  (void)hipFree(d_dprof);
-  (void)hipFree(d_out);
-  (void)hipFree(d_part);
-  (void)hipFree(d_start);
-  if (e != hipSuccess) return hip_fail(e, "potential gradient");
-  for (int a = 0; a < n_atoms; ++a) dL_dxyz[3 * a] = dL_dxyz[3 * a + 1] = dL_dxyz[3 * a + 2] = 0.0;
-  for (int64_t t = 0; t < nt_all; ++t) {  // terms in slice order, atoms' terms in order
-    dL_dxyz[3 * owner[t]] += out[2 * t];
-    dL_dxyz[3 * owner[t] + 1] += out[2 * t + 1];
-  }
+  // terms of one atom are consecutive: its first term
+  std::vector<int64_t> first(std::max(n_atoms, 1), 0);
+  for (int64_t t = nt_all - 1; t >= 0; --t) first[owner[t]] = t;
+  Temps tmp{alloc, st, {}};
+  double* d_terms = tmp.take<double>(terms.size());
+  double* d_prof = tmp.take<double>((size_t)nt_all * (g.ny + g.nx));
+  double* d_dprof = tmp.take<double>((size_t)nt_all * (g.ny + g.nx));
+  double* d_out = tmp.take<double>(2 * (size_t)nt_all);
+  double* d_part = tmp.take<double>((size_t)grad_part_doubles(nt_all, g.ny));
+  int64_t* d_start = tmp.take<int64_t>(start.size());
+  int64_t* d_first = tmp.take<int64_t>(first.size());
+  if (!d_terms || !d_prof || !d_dprof || !d_out || !d_part || !d_start || !d_first)
+    return err(BIP_ENOMEM, "potential gradient temporaries");
+  if (!terms.empty())
+    HIPCHK(hipMemcpyAsync(d_terms, terms.data(), terms.size() * 8, hipMemcpyHostToDevice, st), "terms");
+  HIPCHK(hipMemcpyAsync(d_start, start.data(), start.size() * 8, hipMemcpyHostToDevice, st), "terms");
+  HIPCHK(hipMemcpyAsync(d_first, first.data(), first.size() * 8, hipMemcpyHostToDevice, st), "terms");
+  HIPCHK(launch_profiles(d_terms, nt_all, g.ny, g.nx, g.ly, g.lx, 1, d_prof, d_dprof, st), "profiles");
+  HIPCHK(launch_grad_terms(d_terms, d_prof, d_dprof, d_start, nt_all, (int)most, g.nz, g.ny, g.nx, dL_dV,
+                           d_part, d_out, st),
+         "potential gradient");
+  HIPCHK(launch_atom_grad_sum(d_out, d_first, n_atoms, n_terms, dL_dxyz, st), "potential gradient");
   return BIP_OK;
 }
 

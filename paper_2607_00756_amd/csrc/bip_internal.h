@@ -136,6 +136,11 @@ struct bip_plan {
   std::vector<int32_t> plane_start, plane_atoms;
   int i_min = 0, i_max = 0;
   bool built = false;
+  // S2 streamed in plane segments (window stacks of all atoms above the budget):
+  // segment k covers planes seg_hi[k] .. seg_lo[k] (descending); off2 of an atom is
+  // relative to its segment's block, d_win2 holds one segment
+  bool s2_stream = false;
+  std::vector<int32_t> seg_hi, seg_lo, seg_of;
   int column_batch = 0;  // parent columns per sweep batch of the last build
   int n_cu = 256;        // compute units of the plan's device
   // device buffers
@@ -179,7 +184,13 @@ struct bip_plan {
   std::vector<bip::ProbeJob> h_probe;
   std::vector<int32_t> h_cells;   // cell_start then cell_beams
   std::vector<float2> h_tws;      // twx then twy
-  std::vector<void*> allocations;
+  // device blocks of the plan, all from `alloc` (or hipMallocAsync when it is absent)
+  struct Block { void* ptr; size_t bytes; };
+  std::vector<Block> allocations;
+  bip_alloc alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;  // stream of the latest call (destroy synchronizes it)
+  int64_t bytes_now = 0, bytes_peak = 0;
   // opt-in stage timing with HIP events on the caller's stream
   bool profiling = false;
   struct Timed { int stage; hipEvent_t a, b; };
@@ -198,6 +209,17 @@ enum Stage {
 
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+
+// bip_eels_signal with an optional caller-given workspace (ext_work, ext_bytes):
+// with one, nothing is allocated and requests that do not fit are refused.
+int eels_signal_impl(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
+                     const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy, int32_t scan_sx,
+                     int32_t out_mode, int32_t precision, float* out, void* ext_work, size_t ext_bytes,
+                     void* stream);
+// The S2 transpose sweep over slices j_hi .. j_lo (descending) for every
+// column batch, gathering the windows of the atoms at those planes.  With
+// init, the parents start over from the exit.
+int sweep_s2(bip_plan* p, int j_hi, int j_lo, bool init, hipStream_t st);
 
 // ----------------------------------------------------------- launchers
 // setup (k_setup.hip)
@@ -313,6 +335,9 @@ int64_t grad_part_doubles(int64_t n_terms, int ny);
 hipError_t launch_grad_terms(const double* terms, const double* prof, const double* dprof,
                              const int64_t* start, int64_t nt_all, int most, int nz, int ny, int nx,
                              const float* dV, double* part, double* out, hipStream_t s);
+// dxyz [n_atoms][3] from the per-term outputs; atom a owns terms first[a] .. + n_terms
+hipError_t launch_atom_grad_sum(const double* out, const int64_t* first, int n_atoms, int n_terms,
+                                double* dxyz, hipStream_t s);
 
 // contraction (k_gemm.hip)
 // grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit), (m_tiles,
@@ -330,7 +355,7 @@ hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, 
                              int accumulate, hipStream_t s);
 hipError_t launch_qeels_from_beams(const float* beams_out, const int32_t* bin_start,
                                    const int32_t* bin_list, int ndet, int P, int nq, float* out,
-                                   hipStream_t s);
+                                   int accumulate, hipStream_t s);
 hipError_t launch_zero(float* p, int64_t n, hipStream_t s);
 
 }  // namespace bip

@@ -49,24 +49,59 @@ hipError_t timed(bip_plan* p, int stage, hipStream_t st, F&& launch) {
   return e;
 }
 
-template <typename T>
-int dalloc(bip_plan* p, T** out, size_t count) {
-  *out = nullptr;
-  if (count == 0) return BIP_OK;
+// One device block from the caller's allocator, or stream-ordered from the
+// HIP pool when there is none.
+inline void* raw_alloc(const bip_alloc* al, size_t bytes, hipStream_t s) {
+  if (al && al->alloc) return al->alloc(bytes, (void*)s, al->ctx);
   void* ptr = nullptr;
-  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-  if (e != hipSuccess) {
+  if (hipMallocAsync(&ptr, bytes, s) != hipSuccess) {
     (void)hipGetLastError();
-    return err(BIP_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    return nullptr;
   }
-  p->allocations.push_back(ptr);
-  *out = (T*)ptr;
+  return ptr;
+}
+inline void raw_release(const bip_alloc* al, void* ptr, size_t bytes, hipStream_t s) {
+  if (!ptr) return;
+  if (al && al->release) al->release(ptr, bytes, (void*)s, al->ctx);
+  else (void)hipFreeAsync(ptr, s);
+}
+
+inline const bip_alloc* plan_alloc(const bip_plan* p) { return p->has_alloc ? &p->alloc : nullptr; }
+
+// A block owned by the plan until bip_plan_destroy.
+inline int plan_block(bip_plan* p, void** out, size_t bytes, hipStream_t s) {
+  *out = raw_alloc(plan_alloc(p), bytes, s);
+  if (!*out) return err(BIP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  p->allocations.push_back({*out, bytes});
+  p->bytes_now += (int64_t)bytes;
+  p->bytes_peak = std::max(p->bytes_peak, p->bytes_now);
   return BIP_OK;
+}
+inline void plan_release(bip_plan* p, void* ptr, hipStream_t s) {
+  for (size_t i = 0; i < p->allocations.size(); ++i)
+    if (p->allocations[i].ptr == ptr) {
+      raw_release(plan_alloc(p), ptr, p->allocations[i].bytes, s);
+      p->bytes_now -= (int64_t)p->allocations[i].bytes;
+      p->allocations.erase(p->allocations.begin() + i);
+      return;
+    }
 }
 
 template <typename T>
+int dalloc(bip_plan* p, T** out, size_t count, hipStream_t s) {
+  *out = nullptr;
+  if (count == 0) return BIP_OK;
+  void* ptr = nullptr;
+  int rc = plan_block(p, &ptr, count * sizeof(T), s);
+  *out = (T*)ptr;
+  return rc;
+}
+
+// Copy a host table into a new plan block.  The source must stay alive until
+// the stream has passed the copy.
+template <typename T>
 int upload(bip_plan* p, T** out, const std::vector<T>& v, hipStream_t s) {
-  int rc = dalloc(p, out, v.size());
+  int rc = dalloc(p, out, v.size(), s);
   if (rc) return rc;
   if (!v.empty()) HIPCHK(hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
   return BIP_OK;
@@ -82,20 +117,19 @@ struct Workspace {
   }
 };
 
-inline int ensure_work(bip_plan* p, size_t bytes) {
+// Grow the plan's workspace to `bytes`.  The old block is released in stream
+// order, so no synchronization is needed.
+inline int ensure_work(bip_plan* p, size_t bytes, hipStream_t s) {
   if (p->work_bytes >= bytes) return BIP_OK;
   if (p->d_work) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p->d_work);
+    plan_release(p, p->d_work, s);
     p->d_work = nullptr;
     p->work_bytes = 0;
   }
-  hipError_t e = hipMalloc(&p->d_work, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    p->d_work = nullptr;
-    return err(BIP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes");
-  }
+  void* ptr = nullptr;
+  int rc = plan_block(p, &ptr, bytes, s);
+  if (rc) return rc;
+  p->d_work = ptr;
   p->work_bytes = bytes;
   return BIP_OK;
 }

@@ -561,7 +561,7 @@ __global__ void k_reduce_map(const float* __restrict__ partial, int ntiles, int 
 // qEELS: sum the per-beam intensities over h_y at fixed h_x, in detector order
 __global__ void k_qeels(const float* __restrict__ beams_out, const int32_t* __restrict__ bin_start,
                         const int32_t* __restrict__ bin_list, int ndet, int P, int nq,
-                        float* out) {
+                        float* out, int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)P * nq) return;
   const int rho = (int)(i / nq);
@@ -569,7 +569,7 @@ __global__ void k_qeels(const float* __restrict__ beams_out, const int32_t* __re
   float s = 0.f;
   for (int k = bin_start[q]; k < bin_start[q + 1]; ++k)
     s += beams_out[(int64_t)rho * ndet + bin_list[k]];
-  out[i] = s;
+  out[i] = accumulate ? out[i] + s : s;
 }
 
 template <int PREC, int EPI, bool CONJA, int OPREC = PREC>
@@ -643,10 +643,10 @@ hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, 
 
 hipError_t launch_qeels_from_beams(const float* beams_out, const int32_t* bin_start,
                                    const int32_t* bin_list, int ndet, int P, int nq, float* out,
-                                   hipStream_t s) {
+                                   int accumulate, hipStream_t s) {
   const int64_t n = (int64_t)P * nq;
   hipLaunchKernelGGL(k_qeels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, beams_out,
-                     bin_start, bin_list, ndet, P, nq, out);
+                     bin_start, bin_list, ndet, P, nq, out, accumulate);
   return hipGetLastError();
 }
 

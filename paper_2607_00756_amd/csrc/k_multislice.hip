@@ -268,6 +268,7 @@ hipError_t row_dispatch(int flags, float2* state, int ncols, int ny, const float
     ROW_CASE(ROW_INV | ROW_GATHER_BEFORE_T)
     ROW_CASE(ROW_GATHER_BEFORE_T)
     ROW_CASE(ROW_FWD)
+    ROW_CASE(ROW_INV | ROW_T | ROW_FWD | ROW_SAVE)  // recomputing a checkpoint segment
     ROW_CASE(ROW_INV | ROW_T | ROW_GATHER_AFTER_T | ROW_FWD)
     ROW_CASE(ROW_INV | ROW_T | ROW_GATHER_AFTER_T)
     ROW_CASE(ROW_T | ROW_GATHER_AFTER_T)

@@ -194,7 +194,32 @@ __global__ void k_grad_sum(const double* __restrict__ terms, const double* __res
   out[2 * (int64_t)t + 1] = A * sy;
 }
 
+// dL/d(x, y) of each atom: the sum of its terms (consecutive, starting at
+// first[a]) in term order; dL/dz = 0.
+__global__ void k_atom_sum(const double* __restrict__ out, const int64_t* __restrict__ first,
+                           int n_atoms, int n_terms, double* __restrict__ dxyz) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  double sx = 0.0, sy = 0.0;
+  const int64_t t0 = first[a];
+  for (int k = 0; k < n_terms; ++k) {
+    sx += out[2 * (t0 + k)];
+    sy += out[2 * (t0 + k) + 1];
+  }
+  dxyz[3 * (int64_t)a] = sx;
+  dxyz[3 * (int64_t)a + 1] = sy;
+  dxyz[3 * (int64_t)a + 2] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_atom_grad_sum(const double* out, const int64_t* first, int n_atoms, int n_terms,
+                                double* dxyz, hipStream_t s) {
+  if (n_atoms == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_atom_sum, dim3((n_atoms + 255) / 256), dim3(256), 0, s, out, first, n_atoms,
+                     n_terms, dxyz);
+  return hipGetLastError();
+}
 
 hipError_t launch_profiles(const double* terms, int64_t n_terms, int ny, int nx, double ly,
                            double lx, int deriv, double* prof, double* dprof, hipStream_t s) {

@@ -60,3 +60,22 @@ def test_null_plan_calls_fail_cleanly():
     assert lib.bip_query(None, 0, None) == bip.EINVAL
     assert b"NULL" in lib.bip_last_error()
     lib.bip_plan_destroy(None)
+
+
+def test_allocator_needs_both_callbacks():
+    """A bip_alloc with a missing callback is rejected before anything runs."""
+    from paper_2607_00756_amd import bip
+    half = bip.BipAlloc(bip._ALLOC_FN(lambda n, s, c: None), bip._RELEASE_FN(), None)
+    grid = bip.BipGrid(128, 128, 4, 16.0, 16.0, 2.0)
+    opt = bip.BipOptics(200e3, 0.02, 0.04, 4, 0, 0, 0.0)
+    tau = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    win = (ctypes.c_int32 * 1)(32)
+    org = (ctypes.c_int32 * 2)(0, 0)
+    h = ctypes.c_void_p()
+    rc = bip._lib.bip_plan_create(ctypes.byref(grid), ctypes.byref(opt), 1, tau, win, org,
+                                  ctypes.byref(half), None, ctypes.byref(h))
+    assert rc == bip.EINVAL and b"alloc" in bip._lib.bip_last_error()
+    assert not h.value
+    rc = bip._lib.bip_potential_build(ctypes.byref(grid), 1, tau, 1, tau, tau, None, None, None)
+    assert rc == bip.EINVAL
+

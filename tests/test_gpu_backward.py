@@ -58,7 +58,8 @@ def _gpu_grad(cfg, tp, ibar, recon, dHx=None, dHy=None, batch=None, prec=0):
     tau = plan.eels_backward(tp.n_ch, H, tp.H_off, cfg.scan, Ib, dV, dL_dHconj=gH, dHdx=dx,
                              dHdy=dy, want_tau=dHx is not None, precision=prec)
     torch.cuda.synchronize()
-    out = dV.cpu().numpy().astype(np.float64), gH.cpu().numpy().astype(np.complex128), tau
+    out = (dV.cpu().numpy().astype(np.float64), gH.cpu().numpy().astype(np.complex128),
+           None if tau is None else tau.cpu().numpy())
     plan.close()
     return out
 
@@ -107,6 +108,7 @@ def test_potential_build_and_gradient_match_oracle():
     e = rel_l2(V.cpu().numpy(), Vref)
     dV = r.normal(size=Vref.shape)
     g = bip.potential_grad(grid, xyz, amps, widths, torch.from_numpy(dV.astype(np.float32)).to(dev))
+    g = g.cpu().numpy()
     gref = pot.potential_grad(cfg, xyz, amps, widths, dV.astype(np.float32).astype(np.float64))
     eg = rel_l2(g, gref)
     print(f"[potential] V {e:.2e} grad {eg:.2e}")
@@ -239,8 +241,8 @@ def test_config4_position_gradient_central_differences(c4):
     L0, I0 = L_of(V0, H)
     dV = torch.empty_like(V0)
     tau = plan.eels_backward(sp.n_ch, H, sp.H_off, cfg.scan, (2.0 * (I0 - It)).float().contiguous(), dV,
-                             dHdx=dHx, dHdy=dHy, want_tau=True)
-    g = bip.potential_grad(grid, xyz, amps, widths, dV)
+                             dHdx=dHx, dHdy=dHy, want_tau=True).cpu().numpy()
+    g = bip.potential_grad(grid, xyz, amps, widths, dV).cpu().numpy()
     assert np.all(g[:, 2] == 0.0)
     ion = int(sp.ionized[0])
     d2 = np.sum((xyz[:, :2] - xyz[ion, :2]) ** 2, axis=1)
@@ -293,3 +295,52 @@ def test_backward_with_one_atom_per_workspace_chunk():
     e1, e2 = rel_l2(dV2, dV1), rel_l2(gH2, gH1)
     print(f"[backward chunks] dV {e1:.2e} dH {e2:.2e}")
     assert e1 < 1e-5 and e2 < 1e-5
+
+
+@pytest.mark.parametrize("stride", [2, 3, 7])
+def test_recomputed_checkpoint_segments_match_slice_checkpoints(stride):
+    """ckpt_stride k > 1 keeps every k-th slice and recomputes the others of a
+    segment per column batch: dV, dL/dH and dL/dtau equal the slice-checkpoint
+    gradient bitwise (same kernels on the same data), also with column
+    batching, and match the FP64 oracle gradient."""
+    cfg, tp = _ragged(2)
+    r = np.random.default_rng(4)
+    ibar = r.normal(size=cfg.scan[0] * cfg.scan[1]) * 1e-3
+    prob = as_oracle_problem(tp)
+    dHx = np.concatenate([r.normal(size=(tp.n_ch, w, w)).ravel() for w in tp.win_size]).astype(np.complex64)
+    dHy = np.concatenate([r.normal(size=(tp.n_ch, w, w)).ravel() for w in tp.win_size]).astype(np.complex64)
+    for batch in (None, 3):
+        ref = _gpu_grad(cfg, tp, ibar, E.RECON_MAGNITUDE, dHx, dHy, batch=batch)
+        got = _gpu_grad_stride(cfg, tp, ibar, E.RECON_MAGNITUDE, dHx, dHy, batch, stride)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (stride, batch)
+    # against the oracle gradient (the plan's map at the same dL/dI)
+    It = E.BiP(prob).run(mode=E.OUT_MAP) - 0.5 * ibar
+    want = A.MapGradient(prob).run(It)
+    assert rel_l2(got[0], want["dV"]) < 1e-3
+
+
+def _gpu_grad_stride(cfg, tp, ibar, recon, dHx, dHy, batch, stride):
+    torch, dev = torch_dev()
+    bip = _bip()
+    if batch is not None:
+        os.environ["BIP_COLUMN_BATCH"] = str(batch)
+    try:
+        plan = bip.Plan.from_config(cfg, tp.tau, tp.win_size, tp.win_origin, recon_mode=recon,
+                                    ckpt_stride=stride)
+        V = torch.from_numpy(np.ascontiguousarray(tp.V, np.float32)).to(dev)
+        plan.build_smatrix(V)
+    finally:
+        os.environ.pop("BIP_COLUMN_BATCH", None)
+    H = torch.from_numpy(np.ascontiguousarray(tp.H, np.complex64)).to(dev)
+    dV = torch.empty_like(V)
+    gH = torch.empty_like(H)
+    dx = torch.from_numpy(dHx).to(dev)
+    dy = torch.from_numpy(dHy).to(dev)
+    Ib = torch.from_numpy(np.ascontiguousarray(ibar, np.float32)).to(dev)
+    tau = plan.eels_backward(tp.n_ch, H, tp.H_off, cfg.scan, Ib, dV, dL_dHconj=gH, dHdx=dx, dHdy=dy,
+                             want_tau=True)
+    torch.cuda.synchronize()
+    out = (dV.cpu().numpy().astype(np.float64), gH.cpu().numpy().astype(np.complex128), tau.cpu().numpy())
+    plan.close()
+    return out

@@ -92,3 +92,14 @@ def test_one_atom_per_workspace_chunk():
             assert e1 < 1e-4 and e2 < 1e-4 and d < 1e-5
             assert np.array_equal(many, again)
             plan.close()
+
+
+def test_parent_beyond_nyquist_is_unsupported():
+    """A detector that fills the grid puts parents past the signed index range
+    (beam 31 of a 64-pixel axis has parents 28 and 32 at s = 4), which would
+    alias: plan creation returns BIP_EUNSUPPORTED."""
+    from paper_2607_00756_amd import bip
+    torch_dev()
+    with pytest.raises(bip.BipError) as ei:
+        bip.Plan(64, 64, 2, 8.0, 8.0, 2.0, 200e3, 0.02, 0.45, 4, [[1.0, 1.0, 1.0]], [8], [[0, 0]])
+    assert ei.value.code == bip.EUNSUPPORTED and "outside the grid" in str(ei.value)

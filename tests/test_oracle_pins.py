@@ -343,3 +343,26 @@ def test_on_atom_error_vanishes_at_s1_and_bip_converges_to_exact():
         prob.cfg = dataclasses.replace(cfg, partition=s)
         errs.append(E.rel_l2(E.BiP(prob).run(), exact))
     assert errs[0] < 1e-12 and errs[1] < errs[2]
+
+
+# ------------------------------------ memory-light sweeps and beam chunks
+def test_cropped_sweeps_and_row_chunks_match_full_columns():
+    """s1_windows / s2_windows crop the same sweep as s1_at_planes /
+    s2_at_planes, and BiP.run with detector rows in chunks returns the same
+    intensities (each beam is computed alone)."""
+    cfg = tiny_cfg(ny=32, nx=32, nz=5, ly=8.0, lx=8.0, alpha=30e-3, theta=50e-3, s=2, scan=(4, 4))
+    tp = tiny_problem(cfg, n_atoms=3, n_ch=2, W=6, vscale=100.0, planes=[4, 0, 2])
+    prob = as_oracle_problem(tp)
+    b = E.BiP(prob)
+    planes = [int(i) for i in prob.planes]
+    full1 = ms.s1_at_planes(cfg, b.part1.parents, prob.T, prob.P, planes)
+    full2 = ms.s2_at_planes(cfg, b.part2.parents, prob.T, prob.P, planes)
+    pw = b.parent_windows([0, 1, 2])
+    for a in range(3):
+        assert np.array_equal(pw[a][0], prob.crop(full1[planes[a]], a))
+        assert np.array_equal(pw[a][1], prob.crop(full2[planes[a]], a))
+    ref = b.run(mode=E.OUT_BEAMS)
+    got = b.run(mode=E.OUT_BEAMS, rows=37)
+    assert np.abs(got - ref).max() <= 1e-15 * np.abs(ref).max()
+    sc = [3, 7, 12]
+    assert np.abs(b.run(scans=sc, rows=50) - ref.sum(axis=1)[sc]).max() <= 1e-14 * np.abs(ref).max()
