@@ -194,6 +194,26 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
                     void* stream);
 
 /*
+ * bip_eels_signal_noalloc -- bip_eels_signal for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs and errors as
+ * bip_eels_signal (same kernels); its workspace is a fixed device array of
+ * bip_noalloc_scratch_bytes() bytes (64 MiB) inside the library, which every
+ * device the library runs on holds until the process ends.  The call makes
+ * no allocation of any kind; a request whose workspace exceeds the array is
+ * refused with BIP_EUNSUPPORTED before anything is launched.  Every call on
+ * one device shares that device's array (it keeps the last call's contents;
+ * nothing read is assumed zero): calls that overlap in time on one device
+ * race, so serialize them (one stream, or events).  The plan itself must
+ * have been created beforehand (bip_plan_create allocates).
+ */
+int bip_eels_signal_noalloc(bip_plan* plan, int32_t n_ch, const float* H, const int64_t* H_off,
+                            const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
+                            int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
+                            void* stream);
+size_t bip_noalloc_scratch_bytes(void);
+
+/*
  * bip_eels_backward -- gradient of a map loss (step a16: adjoint of steps
  * a5..a14).  Passage: the forward model's multislice (eq. smatrix-advance,
  * eq. s2), eq. window-recon / eq. magpreserve and eq. coupling / eq. map-sum,

@@ -29,7 +29,8 @@ Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_W
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
            "bip_eels_backward", "bip_potential_build", "bip_potential_grad",
-           "bip_plan_destroy", "bip_last_error"]
+           "bip_plan_destroy", "bip_last_error", "bip_eels_signal_noalloc",
+           "bip_noalloc_scratch_bytes"]
 STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "probe_fold",
           "probe_dft", "det_gemm", "reduce", "gram_gemm"]
 
@@ -121,6 +122,10 @@ _lib.bip_build_smatrix.argtypes = [_p, _p, _p]
 _lib.bip_reconstruct_local.argtypes = [_p, ctypes.c_int32, _p, _p, _p]
 _lib.bip_eels_signal.argtypes = [_p, ctypes.c_int32, _p, _p, _p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p]
+_lib.bip_eels_signal_noalloc.argtypes = _lib.bip_eels_signal.argtypes
+_lib.bip_eels_signal_noalloc.restype = ctypes.c_int
+_lib.bip_noalloc_scratch_bytes.argtypes = []
+_lib.bip_noalloc_scratch_bytes.restype = ctypes.c_size_t
 _lib.bip_parent_windows.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p]
 _lib.bip_query.argtypes = [_p, ctypes.c_int32, _p]
 _lib.bip_set_profiling.argtypes = [_p, ctypes.c_int32]
@@ -223,15 +228,16 @@ class Plan:
         _check(_lib.bip_parent_windows(self._h, atom, which, _ptr(out), _stream(stream)))
 
     def eels_signal(self, n_ch, H, H_off, scan, out_mode, precision, out, atom_subset=None,
-                    stream=None):
-        """H: complex64 device [ragged]; H_off: host int64 [n_atoms+1]."""
+                    stream=None, noalloc=False):
+        """H: complex64 device [ragged]; H_off: host int64 [n_atoms+1].
+        noalloc=True calls bip_eels_signal_noalloc (fixed workspace, no allocation)."""
         offs, op = _host(H_off, np.int64)
         if atom_subset is None:
             sp, ns = ctypes.c_void_p(0), 0
         else:
             sub, sp = _host(atom_subset, np.int32)
             ns = int(sub.size)
-        fn = _lib.bip_eels_signal
+        fn = _lib.bip_eels_signal_noalloc if noalloc else _lib.bip_eels_signal
         _check(fn(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]), int(scan[1]), int(out_mode),
                   int(precision), _ptr(out), _stream(stream)))
 
