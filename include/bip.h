@@ -50,6 +50,7 @@ enum {
 };
 
 enum { BIP_RECON_MAGNITUDE = 0, BIP_RECON_COMPLEX = 1 };
+enum { BIP_PARENTS_LATTICE = 0, BIP_PARENTS_HEX = 1 };
 enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2, BIP_OUT_MAP_DIRECT = 3 };
 enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2, BIP_PREC_FP16 = 3 };
 
@@ -74,6 +75,25 @@ typedef struct bip_optics {
                            bip_eels_signal in plane segments whose windows fit the
                            budget, each segment's atoms contracted before the next
                            segment is swept (one sweep per signal call) */
+  int32_t parent_set;   /* BIP_PARENTS_LATTICE: parents on s Z^2 (`partition`);
+                           BIP_PARENTS_HEX: the paper's hex rings (Alg. 3 build step):
+                           DC plus n_radial rings, ring i (0-based) of n_angular (1 + i)
+                           samples at radius (i + 1) / n_radial of the aperture (S1)
+                           or detector (S2) disc, snapped to the nearest beam of the
+                           set; Sibson weights against the finite parent set, beams
+                           not strictly inside the parents' convex hull taking the
+                           weights of their nearest hull-boundary point */
+  int32_t n_radial, n_angular;  /* hex rings (>= 1 each); ignored for the lattice */
+  int32_t focal;        /* 1: focal back-propagation of S1 (section "Magnitude-preserving
+                           reconstruction and focal back-propagation"): the S1 parent
+                           columns are gathered on an enlarged M x M window (M the
+                           smallest power of two >= 2W, W <= 64), stepped back to the
+                           scattering centroid of the atom's entrance-to-ionization
+                           path (slice mid-depths above the plane weighted by their
+                           projected potential on the window), interpolated there,
+                           and the probe is stepped forward again and cropped to the
+                           window; the steps treat the window as periodic.  Forward
+                           only (bip_eels_backward returns BIP_EUNSUPPORTED). */
 } bip_optics;
 
 typedef struct bip_plan bip_plan;
@@ -192,6 +212,35 @@ int bip_eels_signal(bip_plan* plan, int32_t n_ch, const float* H, const int64_t*
                     const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
                     int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
                     void* stream);
+
+/*
+ * bip_eels_signal_edges -- several ionization edges and the configuration
+ * average in one call, reusing the elastic matrices of the last
+ * bip_build_smatrix.  Passage: the discussion's multi-edge batching and
+ * frozen-phonon averaging (the final intensity is averaged over frozen-phonon
+ * configurations, forward model), both on the same S1/S2 of Alg. 5.
+ *   edges[e]   n_ch, H, H_off, atom_subset, n_subset and out as for
+ *              bip_eels_signal, per edge (e.g. the sites and transition
+ *              potentials of one element's edge); H_off is read only for the
+ *              edge's atoms.
+ *   accumulate 0: out = weight x signal; 1: out += weight x signal, so that
+ *              calls after bip_build_smatrix of each frozen-phonon
+ *              configuration k (with that configuration's H) and weight 1/K
+ *              average the K intensities.
+ * A plan whose S2 is streamed sweeps S2 once per call for all edges.
+ * Errors as bip_eels_signal; BIP_EINVAL for a non-finite weight.
+ */
+typedef struct bip_edge {
+  int32_t n_ch;
+  const float* H;         /* device complex64 ragged [atom][n_ch][W][W] */
+  const int64_t* H_off;   /* host i64 [n_atoms + 1] */
+  const int32_t* atom_subset;  /* host i32 [n_subset], or NULL = all atoms */
+  int32_t n_subset;
+  float* out;             /* device f32, shape of out_mode */
+} bip_edge;
+int bip_eels_signal_edges(bip_plan* plan, int32_t n_edges, const bip_edge* edges, int32_t scan_sy,
+                          int32_t scan_sx, int32_t out_mode, int32_t precision, int32_t accumulate,
+                          float weight, void* stream);
 
 /*
  * bip_eels_signal_noalloc -- bip_eels_signal for callers that cannot

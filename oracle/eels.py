@@ -31,7 +31,7 @@ import numpy as np
 
 from . import multislice as ms
 from . import physics
-from .sibson import Partition
+from .sibson import HexPartition, Partition
 
 RECON_MAGNITUDE = 0
 RECON_COMPLEX = 1
@@ -93,16 +93,61 @@ def reduce_output(cfg, I_dp, det, mode):
     return out                                   # [P, n_q]
 
 
+# --------------------------------------------- focal back-propagation of S1
+def centroid_depth(prob, a):
+    """Depth of the scattering centroid of atom a's entrance-to-ionization
+    path (section "Magnitude-preserving reconstruction and focal
+    back-propagation"; the paper gives no formula).  Reading: the mean depth
+    of the slices above the ionization plane, each slice j at its mid-depth
+    (j + 1/2) dz and weighted by its projected potential summed over the
+    atom's window; with no potential on the path (or at plane 0) the
+    ionization plane itself (no back-propagation)."""
+    cfg = prob.cfg
+    i = int(prob.planes[a])
+    y, x = prob.window(a)
+    m = np.array([float(np.sum(prob.V[j][y[:, None], x[None, :]], dtype=np.float64)) for j in range(i)])
+    if i == 0 or m.sum() <= 0.0:
+        return i * cfg.dz
+    return float(np.sum((np.arange(i) + 0.5) * cfg.dz * m) / m.sum())
+
+
+def focal_window(cfg, W, origin):
+    """The enlarged ("padded") window of the focal step: M x M pixels, M the
+    smallest power of two >= 2W (at most 128), centred on the W x W window:
+    (M, margin, y pixels, x pixels).  Reading: "padded" means a margin of
+    the column's own field around the window, so that the Fresnel step of
+    the window content sees its surroundings; the margin is cropped away
+    after the step."""
+    M = min(128, 1 << (2 * W - 1).bit_length())
+    pad = (M - W) // 2
+    y = (origin[0] - pad + np.arange(M)) % cfg.ny
+    x = (origin[1] - pad + np.arange(M)) % cfg.nx
+    return M, pad, y, x
+
+
+def window_fresnel(cfg, f, dist, sign):
+    """Fresnel step of fields f [..., M, M] on their window, taken as periodic:
+    multiply the window's DFT by exp(sign i pi lambda dist |q|^2), q the
+    frequencies of the window grid (k / (M delta) per axis, signed k).
+    sign = -1 propagates forward by dist (eq. propagator), +1 back."""
+    M = f.shape[-1]
+    lam = physics.wavelength(cfg.energy_ev)
+    qy = physics.signed_index(M) / (M * cfg.ly / cfg.ny)
+    qx = physics.signed_index(M) / (M * cfg.lx / cfg.nx)
+    E = np.exp(sign * 1j * math.pi * lam * dist * (qy[:, None] ** 2 + qx[None, :] ** 2))
+    return np.fft.ifft2(E * np.fft.fft2(f, axes=(-2, -1)), axes=(-2, -1))
+
+
 # -------------------------------------------------------------- contraction
-def contract_probe_order(S1w, S2w, H, C):
+def contract_probe_order(S1w, S2w, H, C, psi=None):
     """Per-beam intensity of one atom, probe order.
 
     S1w [B, W, W], S2w [n_det, W, W], H [n_ch, W, W], C [P, B].
     psi(r, rho) = sum_b S1^b(r) c_b(rho); a_d = sum_r S2^d(r) H_n(r) psi(r, rho);
-    returns sum_n |a_d|^2 as [n_det, P]."""
-    B = S1w.shape[0]
-    K = S1w.shape[1] * S1w.shape[2]
-    psi = S1w.reshape(B, K).T @ C.T               # [K, P]
+    returns sum_n |a_d|^2 as [n_det, P].  psi [K, P] may be given instead."""
+    K = S2w.shape[1] * S2w.shape[2]
+    if psi is None:
+        psi = S1w.reshape(S1w.shape[0], K).T @ C.T   # [K, P]
     S2 = S2w.reshape(S2w.shape[0], K)
     I = np.zeros((S2.shape[0], C.shape[0]))
     for n in range(H.shape[0]):
@@ -247,12 +292,22 @@ class BiP:
     def __init__(self, prob: Problem, recon_mode=RECON_MAGNITUDE):
         self.prob = prob
         cfg = prob.cfg
-        self.part1 = Partition(prob.beams, cfg.partition)
-        self.part2 = Partition(prob.det, cfg.partition)
+        if getattr(cfg, "parents", "lattice") == "hex":
+            # hex-ring parents on the aperture and on the detector disc
+            lam = physics.wavelength(cfg.energy_ev)
+            self.part1 = HexPartition(prob.beams, cfg.n_radial, cfg.n_angular,
+                                      cfg.alpha / lam * cfg.ly, cfg.alpha / lam * cfg.lx)
+            self.part2 = HexPartition(prob.det, cfg.n_radial, cfg.n_angular,
+                                      cfg.theta / lam * cfg.ly, cfg.theta / lam * cfg.lx)
+        else:
+            self.part1 = Partition(prob.beams, cfg.partition)
+            self.part2 = Partition(prob.det, cfg.partition)
         self.recon_mode = recon_mode
+        self.focal = bool(getattr(cfg, "focal", False))
 
     def parent_windows(self, atoms):
-        """{atom: (S1 parent windows [Bp1, W, W], S2 parent windows [Bp2, W, W])}.
+        """{atom: (S1 parent windows [Bp1, W, W], S2 parent windows [Bp2, W, W])};
+        in focal mode the S1 windows are the enlarged M x M ones (focal_window).
 
         The parent columns are propagated in batches and cropped to each
         window as the sweep passes its plane (memory of the windows only)."""
@@ -260,12 +315,37 @@ class BiP:
         cfg = prob.cfg
         atoms = list(atoms)
         wins = [(int(prob.planes[a]),) + tuple(prob.window(a)) for a in atoms]
-        w1 = ms.s1_windows(cfg, self.part1.parents, prob.T, prob.P, wins)
+        wins1 = [(int(prob.planes[a]),) + focal_window(cfg, int(prob.win_size[a]), prob.win_origin[a])[2:]
+                 for a in atoms] if self.focal else wins
+        w1 = ms.s1_windows(cfg, self.part1.parents, prob.T, prob.P, wins1)
         w2 = ms.s2_windows(cfg, self.part2.parents, prob.T, prob.P, wins)
         return {a: [w1[k], w2[k]] for k, a in enumerate(atoms)}
 
+    def focal_probe(self, a, pw, C):
+        """psi [K, P] of atom a with focal back-propagation of S1: the parent
+        columns on the enlarged window are Fresnel-stepped back by the
+        distance from the ionization plane to the scattering centroid,
+        interpolated there (eq. nnw, eq. magpreserve), the probe synthesized,
+        stepped forward by the same distance, and cropped to the atom's
+        window (section "Magnitude-preserving reconstruction and focal
+        back-propagation").  pw[0] holds the enlarged S1 windows."""
+        prob = self.prob
+        cfg = prob.cfg
+        W = int(prob.win_size[a])
+        M, pad, y, x = focal_window(cfg, W, prob.win_origin[a])
+        dist = int(prob.planes[a]) * cfg.dz - centroid_depth(prob, a)
+        back = window_fresnel(cfg, pw[0], dist, +1)
+        s1 = reconstruct(cfg, back, self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+                         self.recon_mode)
+        psi_c = np.tensordot(C, s1, axes=(1, 0))            # [P, M, M] at the centroid
+        psi = window_fresnel(cfg, psi_c, dist, -1)[:, pad:pad + W, pad:pad + W]
+        return psi.reshape(psi.shape[0], W * W).T
+
     def reconstructed(self, a, pw):
-        """(S1~ [B, W, W], S2~ [n_det, W, W]) on the window of atom a."""
+        """(S1~ [B, W, W], S2~ [n_det, W, W]) on the window of atom a (without
+        focal back-propagation)."""
+        if self.focal:
+            raise ValueError("focal mode: S1~ exists only at the centroid, on the enlarged window")
         prob = self.prob
         y, x = prob.window(a)
         s1 = reconstruct(prob.cfg, pw[0], self.part1.parents, self.part1.W, prob.beams, y, x, 1,
@@ -292,19 +372,26 @@ class BiP:
         I_dp = np.zeros((len(prob.det), C.shape[0]))
         parts = {}
         for a in atoms:
+            psi = self.focal_probe(a, pw[a], C) if self.focal else None
+            if psi is not None and order != "probe":
+                raise ValueError("focal back-propagation acts on the probe: probe order only")
+            y, x = prob.window(a)
+            s1 = None if psi is not None else \
+                reconstruct(prob.cfg, pw[a][0], self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+                            self.recon_mode)
             if rows is None:
-                s1, s2 = self.reconstructed(a, pw[a])
-                Ia = contract(s1, s2, prob.H_atom(a), C)
+                s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W, prob.det, y, x,
+                                 2, self.recon_mode)
+                Ia = contract(s1, s2, prob.H_atom(a), C, psi) if psi is not None else \
+                    contract(s1, s2, prob.H_atom(a), C)
             else:
-                y, x = prob.window(a)
-                s1 = reconstruct(prob.cfg, pw[a][0], self.part1.parents, self.part1.W, prob.beams,
-                                 y, x, 1, self.recon_mode)
                 Ia = np.zeros_like(I_dp)
                 for d0 in range(0, len(prob.det), rows):
                     d1 = min(d0 + rows, len(prob.det))
                     s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W[d0:d1],
                                      prob.det[d0:d1], y, x, 2, self.recon_mode)
-                    Ia[d0:d1] = contract(s1, s2, prob.H_atom(a), C)
+                    Ia[d0:d1] = contract(s1, s2, prob.H_atom(a), C, psi) if psi is not None else \
+                        contract(s1, s2, prob.H_atom(a), C)
             if per_atom:
                 parts[a] = Ia
             I_dp += Ia

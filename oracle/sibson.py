@@ -121,3 +121,162 @@ class Partition:
     @property
     def n_parents(self) -> int:
         return self.parents.shape[0]
+
+
+# --------------------------------------------------------------------------
+# Hex-ring parents and Sibson weights against a general parent set
+# (section "Partitioned PRISM-EELS", parent selection and eq. nnw).
+#
+# Parent selection (Alg. 3 build step): the DC beam plus n_radial concentric
+# rings; ring i (i = 0 .. n_radial-1) has radius (i + 1) / n_radial of the
+# disc radius and n_angular (1 + i) samples at angles 2 pi k / (n_angular
+# (1 + i)); each sample is snapped to the nearest beam of the set (ties to the
+# smaller (h_y, h_x)) and duplicates are dropped.  The disc radius is given in
+# beam-index units per axis (q = h / L: radius_y = qmax L_y, radius_x =
+# qmax L_x).
+#
+# Weights: area stealing as above, with the parents a finite set.  The paper
+# states no rule for beams outside the convex hull of the parents, where the
+# Voronoi cell of the query is unbounded.  Reading used: a beam not strictly
+# inside the hull takes the weights of its nearest point on the hull
+# boundary, i.e. linear interpolation between the two ends of the nearest
+# hull edge (the limit of the Sibson coordinates on that edge).
+HULL_EPS = 1e-9
+
+
+def hex_ring_parents(beams, n_radial, n_angular, radius_y, radius_x):
+    """Parent beams [n, 2] (sorted by (h_y, h_x)) of a beam set on its disc."""
+    beams = np.asarray(beams, dtype=np.int64)
+    chosen = set()
+
+    def snap(py, px):
+        d2 = (beams[:, 0] - py) ** 2 + (beams[:, 1] - px) ** 2
+        best = np.flatnonzero(d2 == d2.min())
+        k = min(best, key=lambda i: (beams[i, 0], beams[i, 1]))
+        return int(beams[k, 0]), int(beams[k, 1])
+
+    chosen.add(snap(0.0, 0.0))
+    for i in range(n_radial):
+        frac = (i + 1) / n_radial
+        m = n_angular * (1 + i)
+        for k in range(m):
+            t = 2.0 * np.pi * k / m
+            chosen.add(snap(frac * radius_y * np.sin(t), frac * radius_x * np.cos(t)))
+    return np.array(sorted(chosen), dtype=np.int64).reshape(-1, 2)
+
+
+def convex_hull(points):
+    """Counter-clockwise hull vertices (no collinear points), monotone chain."""
+    pts = sorted(set(map(tuple, np.asarray(points, dtype=float))))
+    if len(pts) < 3:
+        return pts
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+            upper.pop()
+        upper.append(p)
+    return lower[:-1] + upper[:-1]
+
+
+def _hull_projection(x, hull):
+    """(inside strictly?, {vertex: weight}) for the hull rule."""
+    n = len(hull)
+    inside = True
+    best = None
+    for i in range(n):
+        a = np.array(hull[i])
+        b = np.array(hull[(i + 1) % n])
+        e = b - a
+        # signed distance of x to the edge's line (positive inside for CCW order)
+        s = (e[0] * (x[1] - a[1]) - e[1] * (x[0] - a[0])) / np.hypot(e[0], e[1])
+        if s <= HULL_EPS:
+            inside = False
+        t = float(np.clip(np.dot(x - a, e) / np.dot(e, e), 0.0, 1.0))
+        d = np.hypot(*(a + t * e - x))
+        if best is None or d < best[0]:
+            best = (d, tuple(hull[i]), tuple(hull[(i + 1) % n]), t)
+    _, a, b, t = best
+    w = {}
+    for p, v in ((a, 1.0 - t), (b, t)):
+        if v > W_EPS:
+            w[(int(round(p[0])), int(round(p[1])))] = w.get((int(round(p[0])), int(round(p[1]))), 0.0) + v
+    return inside, w
+
+
+def general_weights(x, parents, hull=None):
+    """Sibson weights {(p0, p1): w} of query x against the finite parent set
+    `parents` [n, 2], with the hull rule for queries not strictly inside."""
+    x = np.asarray(x, dtype=float)
+    P = [tuple(map(float, p)) for p in np.asarray(parents)]
+    for p in P:
+        if p[0] == x[0] and p[1] == x[1]:
+            return {(int(p[0]), int(p[1])): 1.0}
+    hull = convex_hull(parents) if hull is None else hull
+    inside, w = _hull_projection(x, hull)
+    if not inside:
+        return w
+    # Voronoi cell of x among the parents and x.  It is bounded (x is strictly
+    # inside the hull) but may reach far out when x is near the hull: start
+    # from a box around x and enlarge it until no vertex of the cell lies on it.
+    span = max(max(abs(p[0] - x[0]), abs(p[1] - x[1])) for p in P)
+    while True:
+        cell = [(x[0] - span, x[1] - span), (x[0] + span, x[1] - span),
+                (x[0] + span, x[1] + span), (x[0] - span, x[1] + span)]
+        for p in P:
+            cell = clip_halfplane(cell, 2.0 * (p[0] - x[0]), 2.0 * (p[1] - x[1]),
+                                  p[0] ** 2 + p[1] ** 2 - x[0] ** 2 - x[1] ** 2)
+        reach = max(max(abs(v[0] - x[0]), abs(v[1] - x[1])) for v in cell)
+        if reach < span * (1.0 - 1e-9):
+            break
+        span *= 8.0
+    total = area(cell)
+    out = {}
+    for p in P:
+        # natural neighbours only: the cell reaches p's bisector with x
+        line = [2.0 * (p[0] - x[0]) * v[0] + 2.0 * (p[1] - x[1]) * v[1] -
+                (p[0] ** 2 + p[1] ** 2 - x[0] ** 2 - x[1] ** 2) for v in cell]
+        if max(line) < -1e-9 * (1.0 + span * span):
+            continue
+        piece = cell
+        for q in P:
+            if q == p:
+                continue
+            piece = clip_halfplane(piece, 2.0 * (q[0] - p[0]), 2.0 * (q[1] - p[1]),
+                                   q[0] ** 2 + q[1] ** 2 - p[0] ** 2 - p[1] ** 2)
+            if len(piece) < 3:
+                break
+        a = area(piece) / total
+        if a > W_EPS:
+            out[(int(p[0]), int(p[1]))] = a
+    return out
+
+
+class HexPartition:
+    """Hex-ring parents and their (sparse) weight matrix for one beam set;
+    same interface as Partition."""
+
+    def __init__(self, beams, n_radial, n_angular, radius_y, radius_x):
+        self.beams = np.asarray(beams, dtype=np.int64)
+        self.parents = hex_ring_parents(self.beams, n_radial, n_angular, radius_y, radius_x)
+        index = {tuple(p): i for i, p in enumerate(self.parents.tolist())}
+        hull = convex_hull(self.parents)
+        rows, cols, vals = [], [], []
+        for b, h in enumerate(self.beams):
+            for p, v in sorted(general_weights(h, self.parents, hull).items()):
+                rows.append(b)
+                cols.append(index[p])
+                vals.append(v)
+        self.W = sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))),
+                               shape=(len(self.beams), len(self.parents)))
+
+    @property
+    def n_parents(self) -> int:
+        return self.parents.shape[0]

@@ -21,6 +21,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
+PARENTS_LATTICE, PARENTS_HEX = 0, 1
 OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT = 0, 1, 2, 3
 PREC_FP32, PREC_SPLIT_BF16, PREC_BF16, PREC_FP16 = 0, 1, 2, 3
 Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
@@ -29,7 +30,7 @@ Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_W
 EXPORTS = ["bip_plan_create", "bip_build_smatrix", "bip_reconstruct_local", "bip_eels_signal",
            "bip_parent_windows", "bip_query", "bip_set_profiling", "bip_stage_timings",
            "bip_eels_backward", "bip_potential_build", "bip_potential_grad",
-           "bip_plan_destroy", "bip_last_error", "bip_eels_signal_noalloc",
+           "bip_plan_destroy", "bip_last_error", "bip_eels_signal_noalloc", "bip_eels_signal_edges",
            "bip_noalloc_scratch_bytes"]
 STAGES = ["transmit", "s1_row", "s1_col", "s2_row", "s2_col", "init", "recon", "probe_fold",
           "probe_dft", "det_gemm", "reduce", "gram_gemm"]
@@ -44,7 +45,14 @@ class BipOptics(ctypes.Structure):
     _fields_ = [("energy_ev", ctypes.c_double), ("alpha_rad", ctypes.c_double),
                 ("theta_rad", ctypes.c_double), ("partition", ctypes.c_int32),
                 ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32),
-                ("s2_window_gb", ctypes.c_double)]
+                ("s2_window_gb", ctypes.c_double), ("parent_set", ctypes.c_int32),
+                ("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32), ("focal", ctypes.c_int32)]
+
+
+class BipEdge(ctypes.Structure):
+    _fields_ = [("n_ch", ctypes.c_int32), ("H", ctypes.c_void_p), ("H_off", ctypes.c_void_p),
+                ("atom_subset", ctypes.c_void_p), ("n_subset", ctypes.c_int32),
+                ("out", ctypes.c_void_p)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -122,6 +130,9 @@ _lib.bip_build_smatrix.argtypes = [_p, _p, _p]
 _lib.bip_reconstruct_local.argtypes = [_p, ctypes.c_int32, _p, _p, _p]
 _lib.bip_eels_signal.argtypes = [_p, ctypes.c_int32, _p, _p, _p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p]
+_lib.bip_eels_signal_edges.argtypes = [_p, ctypes.c_int32, _p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _p]
+_lib.bip_eels_signal_edges.restype = ctypes.c_int
 _lib.bip_eels_signal_noalloc.argtypes = _lib.bip_eels_signal.argtypes
 _lib.bip_eels_signal_noalloc.restype = ctypes.c_int
 _lib.bip_noalloc_scratch_bytes.argtypes = []
@@ -174,13 +185,16 @@ class Plan:
 
     def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
                  win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None,
-                 allocator="torch", s2_window_gb=0.0):
+                 allocator="torch", s2_window_gb=0.0, parents="lattice", n_radial=4, n_angular=6,
+                 focal=False):
         self._h = _p()
         self._built_key = None
         self.allocator, alloc_ref = _alloc_arg(allocator)
         grid = BipGrid(ny, nx, nz, ly, lx, dz)
         self.grid = grid
-        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride, s2_window_gb)
+        opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride, s2_window_gb,
+                        {"lattice": PARENTS_LATTICE, "hex": PARENTS_HEX}[parents], n_radial, n_angular,
+                        1 if focal else 0)
         tau, tp = _host(tau_xyz, np.float64)
         ws, wp = _host(win_size, np.int32)
         wo, op = _host(win_origin, np.int32)
@@ -194,6 +208,10 @@ class Plan:
 
     @classmethod
     def from_config(cls, cfg, tau, win_size, win_origin, **kw):
+        kw.setdefault("parents", getattr(cfg, "parents", "lattice"))
+        kw.setdefault("n_radial", getattr(cfg, "n_radial", 4))
+        kw.setdefault("n_angular", getattr(cfg, "n_angular", 6))
+        kw.setdefault("focal", bool(getattr(cfg, "focal", False)))
         return cls(cfg.ny, cfg.nx, cfg.nz, cfg.ly, cfg.lx, cfg.dz, cfg.energy_ev, cfg.alpha,
                    cfg.theta, cfg.partition, tau, win_size, win_origin, **kw)
 
@@ -240,6 +258,26 @@ class Plan:
         fn = _lib.bip_eels_signal_noalloc if noalloc else _lib.bip_eels_signal
         _check(fn(self._h, int(n_ch), _ptr(H), op, sp, ns, int(scan[0]), int(scan[1]), int(out_mode),
                   int(precision), _ptr(out), _stream(stream)))
+
+    def eels_signal_edges(self, edges, scan, out_mode, precision, accumulate=False, weight=1.0,
+                          stream=None):
+        """Several edges in one call: edges = [(n_ch, H, H_off, atom_subset or None, out), ...];
+        out = weight x signal, or out += weight x signal with accumulate."""
+        keep = []
+        arr = (BipEdge * len(edges))()
+        for i, (n_ch, H, H_off, subset, out) in enumerate(edges):
+            offs, op = _host(H_off, np.int64)
+            keep.append(offs)
+            if subset is None:
+                sp, ns = None, 0
+            else:
+                sub, sp = _host(subset, np.int32)
+                keep.append(sub)
+                ns = int(sub.size)
+            arr[i] = BipEdge(int(n_ch), H.data_ptr(), op, sp, ns, out.data_ptr())
+        _check(_lib.bip_eels_signal_edges(self._h, len(edges), arr, int(scan[0]), int(scan[1]),
+                                          int(out_mode), int(precision), 1 if accumulate else 0,
+                                          float(weight), _stream(stream)))
 
     def eels_backward(self, n_ch, H, H_off, scan, dL_dI, dL_dV, dL_dHconj=None, dHdx=None,
                       dHdy=None, want_tau=False, precision=PREC_FP32, stream=None):

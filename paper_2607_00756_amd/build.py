@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_setup.hip", "k_multislice.hip", "k_recon.hip", "k_probe.hip", "k_gemm.hip", "k_backward.hip", "k_potential.hip", "noalloc.hip", "api.cpp", "backward.cpp"]
+SOURCES = ["k_setup.hip", "k_multislice.hip", "k_recon.hip", "k_probe.hip", "k_gemm.hip", "k_backward.hip", "k_potential.hip", "k_focal.hip", "noalloc.hip", "api.cpp", "backward.cpp"]
 ARCH = "gfx950"
 
 

@@ -137,6 +137,142 @@ int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector
   return BIP_OK;
 }
 
+// Hex-ring parents of a beam set (pairs, sorted by (h_y, h_x)): the DC beam
+// and n_radial rings, ring i (0-based) with n_angular (1 + i) samples at
+// radius (i + 1) / n_radial of the disc (radius_y, radius_x in beam-index
+// units), each snapped to the nearest beam of the set (ties: the smaller
+// (h_y, h_x)), duplicates dropped.
+std::vector<int32_t> hex_ring_parents(const std::vector<int32_t>& beams, int n_radial, int n_angular,
+                                      double radius_y, double radius_x) {
+  const int nb = (int)beams.size() / 2;
+  std::vector<std::pair<int, int>> chosen;
+  auto snap = [&](double py, double px) {
+    double best = 1e300;
+    int bk = 0;
+    for (int b = 0; b < nb; ++b) {
+      const double dy = beams[2 * b] - py, dx = beams[2 * b + 1] - px, d = dy * dy + dx * dx;
+      if (d < best) {  // beams are sorted, so the first of equal distances is the smaller
+        best = d;
+        bk = b;
+      }
+    }
+    chosen.push_back({beams[2 * bk], beams[2 * bk + 1]});
+  };
+  snap(0.0, 0.0);
+  for (int i = 0; i < n_radial; ++i) {
+    const double frac = (double)(i + 1) / n_radial;
+    const int m = n_angular * (1 + i);
+    for (int k = 0; k < m; ++k) {
+      const double t = 2.0 * kPi * k / m;
+      snap(frac * radius_y * std::sin(t), frac * radius_x * std::cos(t));
+    }
+  }
+  std::sort(chosen.begin(), chosen.end());
+  chosen.erase(std::unique(chosen.begin(), chosen.end()), chosen.end());
+  std::vector<int32_t> out;
+  for (auto& c : chosen) {
+    out.push_back(c.first);
+    out.push_back(c.second);
+  }
+  return out;
+}
+
+// Convex hull (counter-clockwise, no collinear vertices) of integer points.
+std::vector<double2> convex_hull(const std::vector<int32_t>& pts) {
+  std::vector<std::pair<long long, long long>> v;
+  for (size_t i = 0; i < pts.size(); i += 2) v.push_back({pts[i], pts[i + 1]});
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  if (v.size() < 3) {
+    std::vector<double2> h;
+    for (auto& q : v) h.push_back(make_double2((double)q.first, (double)q.second));
+    return h;
+  }
+  auto cross = [](std::pair<long long, long long> o, std::pair<long long, long long> a,
+                  std::pair<long long, long long> b) {
+    return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+  };
+  std::vector<std::pair<long long, long long>> lo, up;
+  for (auto& q : v) {
+    while (lo.size() >= 2 && cross(lo[lo.size() - 2], lo.back(), q) <= 0) lo.pop_back();
+    lo.push_back(q);
+  }
+  for (auto it = v.rbegin(); it != v.rend(); ++it) {
+    while (up.size() >= 2 && cross(up[up.size() - 2], up.back(), *it) <= 0) up.pop_back();
+    up.push_back(*it);
+  }
+  lo.pop_back();
+  up.pop_back();
+  std::vector<double2> h;
+  for (auto& q : lo) h.push_back(make_double2((double)q.first, (double)q.second));
+  for (auto& q : up) h.push_back(make_double2((double)q.first, (double)q.second));
+  return h;
+}
+
+// Weights of `query` against the given finite parent set (FP64 kernel) and
+// their CSR, parent indices in the order of `parents`.
+int partition_general(bip_plan* p, const std::vector<int32_t>& query, const std::vector<int32_t>& parents,
+                      std::vector<int32_t>& rowptr, std::vector<int32_t>& col, std::vector<double>& w,
+                      hipStream_t st) {
+  const int nq = (int)query.size() / 2, np = (int)parents.size() / 2;
+  const std::vector<double2> hull = convex_hull(parents);
+  void* tmp[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const size_t tb[5] = {std::max<size_t>(8, query.size() * 4), std::max<size_t>(8, parents.size() * 4),
+                        std::max<size_t>(16, hull.size() * sizeof(double2)),
+                        std::max<size_t>(8, (size_t)nq * 16 * sizeof(int2)),
+                        std::max<size_t>(8, (size_t)nq * 16 * sizeof(double) + 16)};
+  for (int i = 0; i < 5; ++i) {
+    tmp[i] = raw_alloc(plan_alloc(p), tb[i], st);
+    if (!tmp[i]) {
+      for (int k = 0; k < i; ++k) raw_release(plan_alloc(p), tmp[k], tb[k], st);
+      return err(BIP_ENOMEM, "Sibson temporaries");
+    }
+  }
+  int* d_over = (int*)((char*)tmp[4] + (size_t)nq * 16 * sizeof(double));
+  std::vector<int2> slot((size_t)nq * 16);
+  std::vector<double> sw((size_t)nq * 16);
+  int over = 0;
+  hipError_t e = hipMemcpyAsync(tmp[0], query.data(), query.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(tmp[1], parents.data(), parents.size() * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !hull.empty())
+    e = hipMemcpyAsync(tmp[2], hull.data(), hull.size() * sizeof(double2), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(d_over, 0, sizeof(int), st);
+  if (e == hipSuccess)
+    e = launch_sibson_general((const int2*)tmp[0], nq, (const int2*)tmp[1], np, (const double2*)tmp[2],
+                              (int)hull.size(), (int2*)tmp[3], (double*)tmp[4], d_over, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(slot.data(), tmp[3], slot.size() * sizeof(int2), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sw.data(), tmp[4], sw.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&over, d_over, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  for (int i = 0; i < 5; ++i) raw_release(plan_alloc(p), tmp[i], tb[i], st);
+  if (e != hipSuccess) return hip_fail(e, "sibson weights");
+  if (over) return err(BIP_EUNSUPPORTED, "a beam has more than 16 natural-neighbour parents");
+  std::map<std::pair<int, int>, int> index;
+  for (int i = 0; i < np; ++i) index[{parents[2 * i], parents[2 * i + 1]}] = i;
+  rowptr.assign(nq + 1, 0);
+  col.clear();
+  w.clear();
+  for (int q = 0; q < nq; ++q) {
+    std::vector<std::pair<int, double>> row;
+    for (int j = 0; j < 16; ++j) {
+      const size_t i = (size_t)q * 16 + j;
+      if (sw[i] > 1e-12) {
+        auto it = index.find({slot[i].x, slot[i].y});
+        if (it == index.end()) return err(BIP_EHIP, "internal: Sibson slot outside the parent set");
+        row.push_back({it->second, sw[i]});
+      }
+    }
+    std::sort(row.begin(), row.end());
+    for (auto& rw : row) {
+      col.push_back(rw.first);
+      w.push_back(rw.second);
+    }
+    rowptr[q + 1] = (int32_t)col.size();
+  }
+  return BIP_OK;
+}
+
 }  // namespace
 }  // namespace bip
 
@@ -176,6 +312,13 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   if (!(o.energy_ev > 0) || !(o.alpha_rad > 0) || !(o.theta_rad > 0))
     return err(BIP_EINVAL, "energy, alpha and theta must be > 0");
   if (o.partition < 1) return err(BIP_EINVAL, "partition must be >= 1");
+  if (o.parent_set != BIP_PARENTS_LATTICE && o.parent_set != BIP_PARENTS_HEX)
+    return err(BIP_EINVAL, "unknown parent_set");
+  if (o.parent_set == BIP_PARENTS_HEX && (o.n_radial < 1 || o.n_angular < 1))
+    return err(BIP_EINVAL, "hex rings need n_radial >= 1 and n_angular >= 1");
+  if (o.focal != 0 && o.focal != 1) return err(BIP_EINVAL, "focal must be 0 or 1");
+  if (o.focal && o.ckpt_stride != 0)
+    return err(BIP_EUNSUPPORTED, "focal back-propagation is forward only (ckpt_stride must be 0)");
   if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
     return err(BIP_EINVAL, "unknown recon_mode");
   if (o.ckpt_stride < 0) return err(BIP_EINVAL, "ckpt_stride must be >= 0");
@@ -187,6 +330,8 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     if (W < 4 || W > std::min(g.ny, g.nx) || W % 4 != 0)
       return err(BIP_EINVAL, "window size of atom " + std::to_string(a) +
                                  " must be a multiple of 4 in [4, min(ny, nx)]");
+    if (o.focal && (W > 64 || 2 * W > std::min(g.ny, g.nx)))
+      return err(BIP_EUNSUPPORTED, "focal back-propagation needs W <= 64 and 2W <= min(ny, nx)");
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(tau_xyz[3 * a + k]))
         return err(BIP_EINVAL, "non-finite atom position");
@@ -222,8 +367,17 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       p->n_cu = n_cu;
   }
   if (p->B < 1 || p->ndet < 1) return fail(err(BIP_EINVAL, "empty aperture or detector"));
-  if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
-  if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+  if (o.parent_set == BIP_PARENTS_HEX) {
+    p->par1 = hex_ring_parents(p->beams, o.n_radial, o.n_angular, o.alpha_rad / p->lambda * g.ly,
+                               o.alpha_rad / p->lambda * g.lx);
+    p->par2 = hex_ring_parents(p->det, o.n_radial, o.n_angular, o.theta_rad / p->lambda * g.ly,
+                               o.theta_rad / p->lambda * g.lx);
+    if ((rc = partition_general(p, p->beams, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
+    if ((rc = partition_general(p, p->det, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+  } else {
+    if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
+    if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+  }
   p->Bp1 = (int)p->par1.size() / 2;
   p->Bp2 = (int)p->par2.size() / 2;
   // a parent past the signed index range would alias to another frequency of
@@ -245,16 +399,32 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   p->off1.resize(n_atoms);
   p->off2.resize(n_atoms);
   int64_t o1 = 0, o2 = 0;
+  p->focal = o.focal != 0;
+  p->W1.resize(n_atoms);
+  p->oy1.resize(n_atoms);
+  p->ox1.resize(n_atoms);
   for (int a = 0; a < n_atoms; ++a) {
     const int W = win_size[a];
     p->W[a] = W;
     p->oy[a] = ((win_origin[2 * a] % g.ny) + g.ny) % g.ny;
     p->ox[a] = ((win_origin[2 * a + 1] % g.nx) + g.nx) % g.nx;
+    // S1 window: the enlarged M x M one (M the smallest power of two >= 2W),
+    // centred on the atom's window, when S1 is focally back-propagated
+    int M = W;
+    if (p->focal) {
+      M = 8;
+      while (M < 2 * W) M *= 2;
+    }
+    const int pad = (M - W) / 2;
+    p->W1[a] = M;
+    p->oy1[a] = ((p->oy[a] - pad) % g.ny + g.ny) % g.ny;
+    p->ox1[a] = ((p->ox[a] - pad) % g.nx + g.nx) % g.nx;
+    p->focal_max_m = std::max(p->focal_max_m, M);
     const int pl = (int)std::floor(tau_xyz[3 * a + 2] / g.dz);
     p->plane[a] = std::min(std::max(pl, 0), g.nz - 1);
     p->off1[a] = o1;
     p->off2[a] = o2;
-    o1 += (int64_t)p->Bp1 * W * W;
+    o1 += (int64_t)p->Bp1 * M * M;
     o2 += (int64_t)p->Bp2 * W * W;
   }
   p->win1_elems = o1;
@@ -319,7 +489,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   std::vector<GatherRec> grec1(n_atoms), grec2(n_atoms);
   for (int q = 0; q < n_atoms; ++q) {
     const int a = p->plane_atoms[q];
-    grec1[q] = GatherRec{p->W[a], p->oy[a], p->ox[a], 0, p->off1[a]};
+    grec1[q] = GatherRec{p->W1[a], p->oy1[a], p->ox1[a], 0, p->off1[a]};
     grec2[q] = GatherRec{p->W[a], p->oy[a], p->ox[a], 0, p->off2[a]};
   }
   // padded copies of the CSR rows: six (parent, weight) slots, row length, row start
@@ -397,6 +567,13 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
       (rc = dalloc(p, &p->d_win1, (size_t)p->win1_elems, st)) ||
       (rc = dalloc(p, &p->d_win2, (size_t)p->win2_elems, st)))
     return fail(rc);
+  std::vector<FocalAtom> fatoms;
+  if (p->focal) {
+    for (int a = 0; a < n_atoms; ++a)
+      fatoms.push_back(FocalAtom{p->off1[a], p->W1[a], p->W[a], p->oy1[a], p->ox1[a], p->plane[a], a});
+    if ((rc = upload(p, &p->d_fatoms, fatoms, st)) || (rc = dalloc(p, &p->d_fdist, (size_t)n_atoms, st)))
+      return fail(rc);
+  }
   if (o.ckpt_stride >= 1) {
     // one checkpoint per segment of ckpt_stride slices: S1 slices 0 .. i_max-1
     // in segments [mK, mK + K), S2 slices nz-1 .. i_min in segments from the exit
@@ -456,6 +633,14 @@ int bip_build_smatrix(bip_plan* p, const float* V, void* stream) {
                "S1 column pass");
     }
   }
+  // ---- focal back-propagation of the S1 windows to each atom's centroid plane
+  if (p->focal) {
+    HIPCHK(launch_focal_dist(V, p->d_fatoms, p->n_atoms, g.ny, g.nx, g.dz, p->d_fdist, st), "focal distance");
+    HIPCHK(launch_focal_parents(p->d_win1, p->d_fatoms, p->n_atoms, p->d_fdist, p->d_par1, p->Bp1,
+                                p->focal_max_m, g.ny, g.nx, g.ly / g.ny, g.lx / g.nx, p->lambda, p->d_tw, p->L,
+                                st),
+           "focal back-step");
+  }
   // ---- S2: exit -> shallowest ionization plane (transpose multislice);
   // streamed plans sweep S2 inside bip_eels_signal, segment by segment
   if (!p->s2_stream) {
@@ -510,7 +695,7 @@ int bip_parent_windows(bip_plan* p, int32_t atom, int32_t which, float* out, voi
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (which == 2 && p->s2_stream)
     return err(BIP_EUNSUPPORTED, "S2 windows of this plan are streamed inside bip_eels_signal");
-  const int W = p->W[atom];
+  const int W = which == 1 ? p->W1[atom] : p->W[atom];
   const size_t n = (size_t)(which == 1 ? p->Bp1 : p->Bp2) * W * W;
   const float2* src = which == 1 ? p->d_win1 + p->off1[atom] : p->d_win2 + p->off2[atom];
   HIPCHK(hipMemcpyAsync(out, src, n * sizeof(float2), hipMemcpyDeviceToDevice, (hipStream_t)stream),
@@ -525,9 +710,18 @@ int bip_reconstruct_local(bip_plan* p, int32_t atom, float* s1_out, float* s2_ou
   hipStream_t st = (hipStream_t)stream;
   if (s2_out && p->s2_stream)
     return err(BIP_EUNSUPPORTED, "S2 windows of this plan are streamed inside bip_eels_signal");
+  if (s1_out && p->focal)
+    return err(BIP_EUNSUPPORTED, "focal mode: S1 is reconstructed at the centroid plane only");
   if (s1_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 1), (float2*)s1_out, st), "recon S1");
   if (s2_out) HIPCHK(launch_recon_plain(recon_args(p, atom, 2), (float2*)s2_out, st), "recon S2");
   return BIP_OK;
+}
+
+int bip_eels_signal_edges(bip_plan* p, int32_t n_edges, const bip_edge* edges, int32_t scan_sy,
+                          int32_t scan_sx, int32_t out_mode, int32_t precision, int32_t accumulate,
+                          float weight, void* stream) {
+  return bip::signal_edges_impl(p, n_edges, edges, scan_sy, scan_sx, out_mode, precision, accumulate,
+                                weight, nullptr, 0, stream);
 }
 
 int bip_eels_signal(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H_off,
@@ -552,9 +746,16 @@ int bip::eels_signal_impl(bip_plan* p, int32_t n_ch, const float* H, const int64
                           const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy,
                           int32_t scan_sx, int32_t out_mode, int32_t precision, float* out,
                           void* ext_work, size_t ext_bytes, void* stream) {
-  if (!p || !H || !H_off || !out) return err(BIP_EINVAL, "NULL argument");
+  bip_edge e{n_ch, H, H_off, atom_subset, n_subset, out};
+  return signal_edges_impl(p, 1, &e, scan_sy, scan_sx, out_mode, precision, 0, 1.f, ext_work,
+                           ext_bytes, stream);
+}
+
+int bip::signal_edges_impl(bip_plan* p, int32_t n_edges, const bip_edge* edges, int32_t scan_sy,
+                           int32_t scan_sx, int32_t out_mode, int32_t precision, int32_t accumulate,
+                           float weight, void* ext_work, size_t ext_bytes, void* stream) {
+  if (!p || !edges || n_edges < 1) return err(BIP_EINVAL, "NULL argument or no edge");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
-  if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
   if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
   if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)
     return err(BIP_EUNSUPPORTED, "scan raster sides above " + std::to_string(BIP_MAX_SCAN));
@@ -564,46 +765,96 @@ int bip::eels_signal_impl(bip_plan* p, int32_t n_ch, const float* H, const int64
   if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16 &&
       precision != BIP_PREC_FP16)
     return err(BIP_EINVAL, "unknown precision");
-  for (int a = 0; a < p->n_atoms; ++a)
-    if (H_off[a + 1] - H_off[a] != (int64_t)n_ch * p->W[a] * p->W[a] || H_off[a] < 0)
-      return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
-  std::vector<int32_t> atoms;
-  if (atom_subset) {
-    if (n_subset < 0) return err(BIP_EINVAL, "n_subset < 0");
-    for (int i = 0; i < n_subset; ++i) {
-      if (atom_subset[i] < 0 || atom_subset[i] >= p->n_atoms)
-        return err(BIP_EINVAL, "atom_subset entry out of range");
-      atoms.push_back(atom_subset[i]);
+  if (!std::isfinite(weight)) return err(BIP_EINVAL, "weight must be finite");
+  const bool weighted = accumulate || weight != 1.f;
+  if (weighted && ext_work) return err(BIP_EUNSUPPORTED, "accumulate/weight need a workspace");
+  std::vector<std::vector<int32_t>> atoms(n_edges);
+  for (int e = 0; e < n_edges; ++e) {
+    const bip_edge& E = edges[e];
+    if (!E.H || !E.H_off || !E.out) return err(BIP_EINVAL, "NULL argument in edge " + std::to_string(e));
+    if (E.n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
+    if (E.atom_subset) {
+      if (E.n_subset < 0) return err(BIP_EINVAL, "n_subset < 0");
+      for (int i = 0; i < E.n_subset; ++i) {
+        if (E.atom_subset[i] < 0 || E.atom_subset[i] >= p->n_atoms)
+          return err(BIP_EINVAL, "atom_subset entry out of range");
+        atoms[e].push_back(E.atom_subset[i]);
+      }
+    } else {
+      for (int a = 0; a < p->n_atoms; ++a) atoms[e].push_back(a);
     }
-  } else {
-    for (int a = 0; a < p->n_atoms; ++a) atoms.push_back(a);
+    for (int a : atoms[e])  // only the atoms an edge contracts read its H
+      if (E.H_off[a + 1] - E.H_off[a] != (int64_t)E.n_ch * p->W[a] * p->W[a] || E.H_off[a] < 0)
+        return err(BIP_EINVAL, "H_off inconsistent with n_ch and the window of atom " + std::to_string(a));
   }
   hipStream_t st = (hipStream_t)stream;
   p->stream = st;
-  if (!p->s2_stream)
-    return signal_atoms(p, atoms, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
-                        ext_bytes, false, st);
-  // S2 streamed: sweep a plane segment, contract its atoms (in the listed
-  // order), then the next segment; the outputs accumulate over the segments
+  const int P = scan_sy * scan_sx;
+  const int64_t n_out = out_mode == BIP_OUT_QEELS ? (int64_t)P * p->nq
+                        : out_mode == BIP_OUT_BEAMS ? (int64_t)P * p->ndet : (int64_t)P;
+  // weighted / accumulating calls contract into a plan-owned block, then add
+  // weight times it into the edge's output
+  float* tmp = nullptr;
+  if (weighted) {
+    if (p->tmp_bytes < (size_t)n_out * 4) {
+      if (p->d_tmp) plan_release(p, p->d_tmp, st);
+      p->d_tmp = nullptr;
+      p->tmp_bytes = 0;
+      void* ptr = nullptr;
+      int rc = plan_block(p, &ptr, (size_t)n_out * 4, st);
+      if (rc) return rc;
+      p->d_tmp = (float*)ptr;
+      p->tmp_bytes = (size_t)n_out * 4;
+    }
+    tmp = p->d_tmp;
+  }
+  std::vector<int> contributions(n_edges, 0);
+  // one edge's atoms of a segment (seg < 0: every atom of the edge)
+  auto run = [&](int e, const std::vector<int32_t>& list) -> int {
+    const bip_edge& E = edges[e];
+    if (!weighted) {
+      int rc = signal_atoms(p, list, E.n_ch, E.H, E.H_off, scan_sy, scan_sx, out_mode, precision, E.out,
+                            ext_work, ext_bytes, contributions[e] > 0, st);
+      ++contributions[e];
+      return rc;
+    }
+    int rc = signal_atoms(p, list, E.n_ch, E.H, E.H_off, scan_sy, scan_sx, out_mode, precision, tmp,
+                          nullptr, 0, false, st);
+    if (rc) return rc;
+    HIPCHK(launch_axpy(E.out, tmp, n_out, weight, accumulate || contributions[e] > 0, st), "weighted sum");
+    ++contributions[e];
+    return BIP_OK;
+  };
+  if (!p->s2_stream) {
+    for (int e = 0; e < n_edges; ++e) {
+      int rc = run(e, atoms[e]);
+      if (rc) return rc;
+    }
+    return BIP_OK;
+  }
+  // S2 streamed: sweep a plane segment, contract its atoms of every edge (in
+  // each edge's listed order), then the next segment; the outputs accumulate
+  // over the segments
   int last = -1;
-  for (int a : atoms) last = std::max(last, p->seg_of[a]);
-  int calls = 0;
+  for (auto& l : atoms)
+    for (int a : l) last = std::max(last, p->seg_of[a]);
   for (int k = 0; k <= last; ++k) {
     const int j_from = k == 0 ? p->g.nz - 1 : p->seg_lo[k - 1] - 1;
     int rc = sweep_s2(p, j_from, p->seg_lo[k], k == 0, st);
     if (rc) return rc;
-    std::vector<int32_t> seg;
-    for (int a : atoms)
-      if (p->seg_of[a] == k) seg.push_back(a);
-    if (seg.empty()) continue;
-    rc = signal_atoms(p, seg, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
-                      ext_bytes, calls > 0, st);
-    if (rc) return rc;
-    ++calls;
+    for (int e = 0; e < n_edges; ++e) {
+      std::vector<int32_t> seg;
+      for (int a : atoms[e])
+        if (p->seg_of[a] == k) seg.push_back(a);
+      if (seg.empty()) continue;
+      rc = run(e, seg);
+      if (rc) return rc;
+    }
   }
-  if (calls == 0)  // no atom selected: the outputs are zero
-    return signal_atoms(p, {}, n_ch, H, H_off, scan_sy, scan_sx, out_mode, precision, out, ext_work,
-                        ext_bytes, false, st);
+  for (int e = 0; e < n_edges; ++e)  // an edge without atoms: its outputs are zero (or unchanged)
+    if (contributions[e] == 0 && !accumulate) {
+      HIPCHK(launch_zero(edges[e].out, n_out, st), "zero");
+    }
   return BIP_OK;
 }
 
@@ -635,17 +886,20 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   auto n1_of = [](int W) { return roundup((int64_t)W * W, 128); };  // ... to whole tiles
   auto ldf_of = [](int W) { return roundup((int64_t)W * W, 64); };  // DFT workspace pitch
   // per-atom blocks, in buffer order: [0] DFT workspace (complex64 elements),
-  // [1..3] contraction operands (plane elements)
-  auto sizes = [&](int W, int64_t* s) {
-    s[0] = (int64_t)P * ldf_of(W);                                 // X [S_y][S_x][r]
+  // [1..3] contraction operands (plane elements), [4] in focal mode the probe
+  // at the centroid on the enlarged window (FP32 planes)
+  auto sizes = [&](int a, int64_t* s) {
+    const int W = p->W[a], W1 = p->W1[a];
+    s[0] = (int64_t)P * ldf_of(W1);                                // X [S_y][S_x][r] (S1 window)
     s[1] = gram ? n1_of(W) * Dk : Dpad * kd_of(W);                 // S2~^T [r][d] | S2~ [d][r]
     s[2] = gram ? n1_of(W) * kd_of(W) : (int64_t)n_ch * Ppad * kd_of(W);  // Q [r][r'] | U_n [rho][r]
     s[3] = gram ? Ppad * kd_of(W) : 0;                             // psi^T [rho][r]
+    s[4] = p->focal ? Ppad * kd_of(W1) : 0;                        // psi at the centroid
   };
   auto atom_bytes = [&](int a) {
-    int64_t s[4];
-    sizes(p->W[a], s);
-    return s[0] * 8 + (s[1] + s[2] + s[3]) * csz;
+    int64_t s[5];
+    sizes(a, s);
+    return s[0] * 8 + (s[1] + s[2] + s[3]) * csz + s[4] * 8;
   };
   int max_n1_all = 0;
   for (int a : atoms) max_n1_all = std::max<int>(max_n1_all, (int)n1_of(p->W[a]));
@@ -683,7 +937,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   const int64_t fixed = n_partial_tiles * Ppad * 4 +
                         (out_mode == BIP_OUT_QEELS ? (int64_t)P * p->ndet * 4 : 0) +
                         n_jobs_total * (int64_t)sizeof(GemmJob) +
-                        (int64_t)atoms.size() * (int64_t)sizeof(ProbeJob) +
+                        (int64_t)atoms.size() * (int64_t)(sizeof(ProbeJob) + sizeof(FocalProbeJob)) + 64 +
                         (int64_t)cells.size() * 4 + (int64_t)tws.size() * 8 + (1 << 20);
   // chunking: consecutive atoms while the per-chunk operands fit the budget
   std::vector<std::pair<int, int>> chunks;
@@ -731,6 +985,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   int32_t* d_cells = (int32_t*)ws.take(cells.size() * 4);
   float2* d_tws = (float2*)ws.take(tws.size() * 8);
   ReconAtom* d_ratoms = (ReconAtom*)ws.take(atoms.size() * sizeof(ReconAtom));
+  FocalProbeJob* d_fjobs = p->focal ? (FocalProbeJob*)ws.take(atoms.size() * sizeof(FocalProbeJob) + 64) : nullptr;
   const size_t chunk_base = ws.used;
   if (ws.used > work_cap) return err(BIP_ENOMEM, "internal: tables exceed the workspace");
   HIPCHK(hipMemcpyAsync(d_cells, cells.data(), cells.size() * 4, hipMemcpyHostToDevice, st), "cells");
@@ -744,21 +999,23 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   jprobe.clear();
   jdet.clear();
   jquad.clear();
-  std::vector<int64_t> off[4];
-  std::vector<int64_t> chunk_plane[4];
+  std::vector<int64_t> off[5];
+  std::vector<int64_t> chunk_plane[5];
   for (auto& v : chunk_plane) v.assign(chunks.size(), 0);
   for (size_t c = 0; c < chunks.size(); ++c) {
-    int64_t acc[4] = {0, 0, 0, 0};
+    int64_t acc[5] = {0, 0, 0, 0, 0};
     for (int i = chunks[c].first; i < chunks[c].second; ++i) {
-      int64_t s[4];
-      sizes(p->W[atoms[i]], s);
-      for (int k = 0; k < 4; ++k) {
+      int64_t s[5];
+      sizes(atoms[i], s);
+      for (int k = 0; k < 5; ++k) {
         off[k].push_back(acc[k]);
         acc[k] += s[k];
       }
     }
-    for (int k = 0; k < 4; ++k) chunk_plane[k][c] = acc[k];
+    for (int k = 0; k < 5; ++k) chunk_plane[k][c] = acc[k];
   }
+  std::vector<FocalProbeJob>& jfocal = p->h_fjobs;
+  jfocal.clear();
   std::vector<int64_t> det_first(atoms.size());
   for (size_t i = 0; i < atoms.size(); ++i) {
     const int a = atoms[i];
@@ -774,6 +1031,17 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     pj.ox = p->ox[a];
     pj.kd = kd;
     pj.ldf = (int32_t)ldf_of(W);
+    if (p->focal) {  // the probe at the centroid on the enlarged window, then the forward step
+      const int W1 = p->W1[a];
+      pj.out_off = off[4][i];
+      pj.W = W1;
+      pj.oy = p->oy1[a];
+      pj.ox = p->ox1[a];
+      pj.kd = (int32_t)kd_of(W1);
+      pj.ldf = (int32_t)ldf_of(W1);
+      jfocal.push_back(FocalProbeJob{off[4][i], gram ? off[3][i] : off[2][i], H_off[a], W1, W, kd,
+                                     (int32_t)kd_of(W1), a, 0});
+    }
     jprobe.push_back(pj);
     det_first[i] = (int64_t)jdet.size();
     if (gram) {
@@ -827,6 +1095,9 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   GemmJob* d_jdet = d_jobs;
   GemmJob* d_jquad = d_jdet + jdet.size();
   HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
+  if (p->focal && !jfocal.empty())
+    HIPCHK(hipMemcpyAsync(d_fjobs, jfocal.data(), jfocal.size() * sizeof(FocalProbeJob), hipMemcpyHostToDevice, st),
+           "jobs");
   HIPCHK(hipMemcpyAsync(d_jdet, jdet.data(), jdet.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   if (!jquad.empty())
     HIPCHK(hipMemcpyAsync(d_jquad, jquad.data(), jquad.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
@@ -857,24 +1128,26 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   for (size_t c = 0; c < chunks.size(); ++c) {
     ws.used = chunk_base;
     const int64_t pl0 = chunk_plane[0][c], pl1 = chunk_plane[1][c], pl2 = chunk_plane[2][c],
-                  pl3 = chunk_plane[3][c];
+                  pl3 = chunk_plane[3][c], pl4 = chunk_plane[4][c];
     float2* X = (float2*)ws.take(pl0 * 8);
     char* S2op = (char*)ws.take(pl1 * csz);
     char* X2 = (char*)ws.take(pl2 * csz);   // Q (Gram) or U (direct)
     char* PsiT = (char*)ws.take(std::max<int64_t>(pl3, 1) * csz);
+    float* PsiC = p->focal ? (float*)ws.take(std::max<int64_t>(pl4, 1) * 8) : nullptr;
     if (ws.used > work_cap) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
-    int max_n1 = 0, max_w2 = 0, max_kd = 0;
+    int max_n1 = 0, max_w2 = 0, max_kd = 0, max_m = 0;
     const int c0 = chunks[c].first, c1 = chunks[c].second, nat = c1 - c0;
     for (int i = c0; i < c1; ++i) {
       const int a = atoms[i];
-      const int W = p->W[a];
-      int64_t s[4];
-      sizes(W, s);
+      const int W = p->W[a], W1 = p->W1[a];
+      int64_t s[5];
+      sizes(a, s);
       max_n1 = std::max<int>(max_n1, (int)n1_of(W));
-      max_w2 = std::max(max_w2, W * W);
-      max_kd = std::max<int>(max_kd, (int)kd_of(W));
+      max_w2 = std::max(max_w2, W1 * W1);
+      max_kd = std::max<int>(max_kd, (int)kd_of(W1));
+      max_m = std::max(max_m, W1);
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
-          off[3][i] + s[3] > pl3)
+          off[3][i] + s[3] > pl3 || off[4][i] + s[4] > pl4)
         return err(BIP_EINVAL, "internal: operand block outside its buffer");
       if (gram && !recon_batched) {
         ReconArgs ra = recon_args(p, a, 2);
@@ -907,8 +1180,35 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     pa.out_plane = gram ? pl3 : pl2;
     HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, max_w2, nat, st); }),
            "probe fold");
-    HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),
-           "probe synthesis");
+    if (!p->focal) {
+      HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),
+             "probe synthesis");
+    } else {
+      // the probe at the centroid (FP32) on the enlarged window, then its forward
+      // step to the ionization plane, cropped to the window, into the operand
+      pa.out = PsiC;
+      pa.out_plane = pl4;
+      HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, BIP_PREC_FP32, false, max_kd, nat, st); }),
+             "probe synthesis");
+      FocalProbeArgs fp{};
+      fp.jobs = d_fjobs + c0;
+      fp.psi_c = PsiC;
+      fp.psi_plane = pl4;
+      fp.out = gram ? (void*)PsiT : (void*)X2;
+      fp.out_plane = gram ? pl3 : pl2;
+      fp.H = (const float2*)H;
+      fp.n_ch = n_ch;
+      fp.P = P;
+      fp.Ppad = (int)Ppad;
+      fp.L = p->L;
+      fp.tw = p->d_tw;
+      fp.dy = p->g.ly / p->g.ny;
+      fp.dx = p->g.lx / p->g.nx;
+      fp.lambda = p->lambda;
+      fp.dist = p->d_fdist;
+      HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_focal_probe(fp, precision, !gram, nat, max_m, st); }),
+             "focal probe step");
+    }
     GemmArgs g{};
     g.H = (const float2*)H;
     g.n_ch = n_ch;

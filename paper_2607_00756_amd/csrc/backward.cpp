@@ -57,6 +57,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   if (!p || !H || !H_off || !dL_dI || !dL_dV) return err(BIP_EINVAL, "NULL argument");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (!p->d_ckpt2) return err(BIP_ESTATE, "plan created without slice checkpoints (ckpt_stride 0)");
+  if (p->focal) return err(BIP_EUNSUPPORTED, "focal back-propagation is forward only");
   if (n_ch < 1) return err(BIP_EINVAL, "n_ch must be >= 1");
   if (scan_sy < 1 || scan_sx < 1) return err(BIP_EINVAL, "scan raster must be >= 1 x 1");
   if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)

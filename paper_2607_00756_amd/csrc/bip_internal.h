@@ -117,6 +117,34 @@ struct ProbeArgs {
   int n_ch;
 };
 
+// Focal back-propagation of S1: one atom's enlarged window and its plane.
+struct FocalAtom {
+  int64_t win_off;  // the atom's S1 parent windows [Bp1][M][M] in the window stack
+  int32_t M, W;     // enlarged window side (power of two) and the atom's window side
+  int32_t oy, ox;   // enlarged window origin (pixels, mod N)
+  int32_t plane, atom;
+};
+
+struct FocalProbeJob {
+  int64_t psi_off;  // the atom's psi at the centroid [Ppad][kd_c] (FP32 planes)
+  int64_t out_off;  // the atom's operand block (plane elements)
+  int64_t h_off;    // first H element of the atom
+  int32_t M, W, kd, kd_c, atom, pad;
+};
+
+struct FocalProbeArgs {
+  const FocalProbeJob* jobs;
+  const float* psi_c;
+  int64_t psi_plane;
+  void* out;
+  int64_t out_plane;
+  const float2* H;
+  int n_ch, P, Ppad, L;
+  const float2* tw;       // exp(-2 pi i m / L)
+  double dy, dx, lambda;  // pixel sizes (A) and wavelength (A)
+  const double* dist;     // back-step distance of each atom (A)
+};
+
 }  // namespace bip
 
 struct bip_plan {
@@ -159,6 +187,13 @@ struct bip_plan {
   int32_t *d_tstart2 = nullptr, *d_tpar2 = nullptr, *d_eloc2 = nullptr;
   int tile_np1 = 0, tile_np2 = 0;  // most distinct parents of any 64-beam tile
   int32_t *d_W = nullptr, *d_oy = nullptr, *d_ox = nullptr;
+  // S1 windows: the atom's own (W, oy, ox), or the enlarged focal ones
+  bool focal = false;
+  std::vector<int32_t> W1, oy1, ox1;
+  int focal_max_m = 0;
+  bip::FocalAtom* d_fatoms = nullptr;
+  double* d_fdist = nullptr;       // back-step distance per atom (A), set by each build
+  std::vector<bip::FocalProbeJob> h_fjobs;
   int64_t *d_off1 = nullptr, *d_off2 = nullptr;
   bip::GatherRec *d_grec1 = nullptr, *d_grec2 = nullptr;  // gather records in plane order
   float2* d_state1 = nullptr;   // [Bp1][G]
@@ -177,6 +212,8 @@ struct bip_plan {
   // signal workspace (grown on demand)
   void* d_work = nullptr;
   size_t work_bytes = 0;
+  float* d_tmp = nullptr;  // output of weighted / accumulated signals before the sum
+  size_t tmp_bytes = 0;
   // host tables read by asynchronous copies; kept alive until the next call
   std::vector<bip::GemmJob> h_jobs2, h_jobs3;
   std::vector<bip::ReconAtom> h_ratoms;
@@ -216,6 +253,13 @@ int eels_signal_impl(bip_plan* p, int32_t n_ch, const float* H, const int64_t* H
                      const int32_t* atom_subset, int32_t n_subset, int32_t scan_sy, int32_t scan_sx,
                      int32_t out_mode, int32_t precision, float* out, void* ext_work, size_t ext_bytes,
                      void* stream);
+// Several edges (each its own H, channels, atoms and output) in one call;
+// accumulate / weight: out += weight x signal (out = weight x signal when not
+// accumulating).  With a caller-given workspace only weight 1 without
+// accumulation is served.
+int signal_edges_impl(bip_plan* p, int32_t n_edges, const bip_edge* edges, int32_t scan_sy,
+                      int32_t scan_sx, int32_t out_mode, int32_t precision, int32_t accumulate,
+                      float weight, void* ext_work, size_t ext_bytes, void* stream);
 // The S2 transpose sweep over slices j_hi .. j_lo (descending) for every
 // column batch, gathering the windows of the atoms at those planes.  With
 // init, the parents start over from the exit.
@@ -235,6 +279,11 @@ hipError_t launch_init_planewaves_rowft(float2* state, const int2* h, int nb, in
                                         const float2* tw, int L, float scale, hipStream_t s);
 hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p, double* slot_w,
                          hipStream_t st);
+// against a finite parent set with its convex hull (CCW); *overflow set when a
+// query has more than 16 natural neighbours
+hipError_t launch_sibson_general(const int2* query, int nq, const int2* parents, int np,
+                                 const double2* hull, int nh, int2* slot_p, double* slot_w,
+                                 int* overflow, hipStream_t st);
 
 // multislice (k_multislice.hip)
 enum RowFlags {
@@ -323,6 +372,15 @@ hipError_t launch_recon_adjoint(const ReconArgs& a, int side, const float2* gsrc
                                 const int32_t* tp_b, const float* tp_w, float2* gwin,
                                 hipStream_t s);
 
+// focal back-propagation (k_focal.hip)
+hipError_t launch_focal_dist(const float* V, const FocalAtom* atoms, int n_atoms, int ny, int nx,
+                             double dz, double* dist, hipStream_t s);
+hipError_t launch_focal_parents(float2* win, const FocalAtom* atoms, int n_atoms, const double* dist,
+                                const int2* parents, int n_par, int max_m, int ny, int nx, double dy,
+                                double dx, double lambda, const float2* tw, int L, hipStream_t s);
+hipError_t launch_focal_probe(const FocalProbeArgs& fp, int prec, bool u, int n_jobs, int max_m,
+                              hipStream_t s);
+
 // slice potentials (k_potential.hip).  Terms are (x, y, A, w) quadruples
 // grouped by slice: slice z holds terms start[z] .. start[z + 1] (device i64).
 hipError_t launch_profiles(const double* terms, int64_t n_terms, int ny, int nx, double ly,
@@ -357,5 +415,7 @@ hipError_t launch_qeels_from_beams(const float* beams_out, const int32_t* bin_st
                                    const int32_t* bin_list, int ndet, int P, int nq, float* out,
                                    int accumulate, hipStream_t s);
 hipError_t launch_zero(float* p, int64_t n, hipStream_t s);
+// out = (accumulate ? out : 0) + w x src
+hipError_t launch_axpy(float* out, const float* src, int64_t n, float w, int accumulate, hipStream_t s);
 
 }  // namespace bip

@@ -201,9 +201,9 @@ inline ReconArgs recon_args(const bip_plan* p, int a, int side) {
   r.scale = 1.f;
   r.beams = side == 1 ? p->d_beams : p->d_det;
   r.nb = side == 1 ? p->B : p->ndet;
-  r.W = p->W[a];
-  r.oy = p->oy[a];
-  r.ox = p->ox[a];
+  r.W = side == 1 ? p->W1[a] : p->W[a];  // S1: the enlarged window in focal mode
+  r.oy = side == 1 ? p->oy1[a] : p->oy[a];
+  r.ox = side == 1 ? p->ox1[a] : p->ox[a];
   r.ny = p->g.ny;
   r.nx = p->g.nx;
   r.tw = p->d_tw;

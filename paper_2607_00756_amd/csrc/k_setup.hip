@@ -207,6 +207,158 @@ hipError_t launch_sibson(const int2* query, int nq, int s_lattice, int2* slot_p,
   return hipGetLastError();
 }
 
+// Sibson coordinates against a finite parent set (hex-ring parents).  The
+// cell of x and the pieces of its natural neighbours are clipped against
+// every parent.
+// Queries not strictly inside the parents' convex hull (hull: CCW vertices)
+// take the weights of their nearest hull-boundary point: linear interpolation
+// between the two ends of the nearest hull edge.  FP64.
+namespace {
+constexpr int kGenVerts = 48;
+constexpr double kHullEps = 1e-9;
+
+struct GPoly {
+  double x[kGenVerts], y[kGenVerts];
+  int n;
+};
+
+__device__ inline void gclip(const GPoly& in, double a, double b, double c, GPoly& out) {
+  out.n = 0;
+  for (int i = 0; i < in.n; ++i) {
+    const int k = (i + 1 == in.n) ? 0 : i + 1;
+    const double px = in.x[i], py = in.y[i], qx = in.x[k], qy = in.y[k];
+    const double fp = a * px + b * py - c, fq = a * qx + b * qy - c;
+    if (fp <= 0.0 && out.n < kGenVerts) {
+      out.x[out.n] = px;
+      out.y[out.n] = py;
+      ++out.n;
+    }
+    if (((fp < 0.0 && fq > 0.0) || (fp > 0.0 && fq < 0.0)) && out.n < kGenVerts) {
+      const double t = fp / (fp - fq);
+      out.x[out.n] = px + t * (qx - px);
+      out.y[out.n] = py + t * (qy - py);
+      ++out.n;
+    }
+  }
+}
+
+__device__ inline double garea(const GPoly& p) {
+  if (p.n < 3) return 0.0;
+  double s = 0.0;
+  for (int i = 0; i < p.n; ++i) {
+    const int k = (i + 1 == p.n) ? 0 : i + 1;
+    s += p.x[i] * p.y[k] - p.x[k] * p.y[i];
+  }
+  return fabs(s) * 0.5;
+}
+}  // namespace
+
+__global__ void k_sibson_general(const int2* __restrict__ query, int nq, const int2* __restrict__ par,
+                                 int np, const double2* __restrict__ hull, int nh, int2* slot_p,
+                                 double* slot_w, int* overflow) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int2 h = query[q];
+  int2* sp = slot_p + (size_t)q * 16;
+  double* sw = slot_w + (size_t)q * 16;
+  for (int k = 0; k < 16; ++k) {
+    sp[k] = make_int2(0, 0);
+    sw[k] = 0.0;
+  }
+  const double x0 = h.x, x1 = h.y;
+  for (int i = 0; i < np; ++i)
+    if (par[i].x == h.x && par[i].y == h.y) {  // query coincides with a parent
+      sp[0] = par[i];
+      sw[0] = 1.0;
+      return;
+    }
+  // hull rule
+  bool inside = nh >= 3;
+  double best = 1e300;
+  int be = 0;
+  double bt = 0.0;
+  for (int i = 0; i < nh; ++i) {
+    const double2 a = hull[i], b = hull[(i + 1) % nh];
+    const double ex = b.x - a.x, ey = b.y - a.y;
+    const double s = (ex * (x1 - a.y) - ey * (x0 - a.x)) / sqrt(ex * ex + ey * ey);
+    if (s <= kHullEps) inside = false;
+    double t = ((x0 - a.x) * ex + (x1 - a.y) * ey) / (ex * ex + ey * ey);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    const double dx = a.x + t * ex - x0, dy = a.y + t * ey - x1;
+    const double d = sqrt(dx * dx + dy * dy);
+    if (d < best) {
+      best = d;
+      be = i;
+      bt = t;
+    }
+  }
+  if (!inside) {
+    const double2 a = hull[be], b = hull[(be + 1) % nh];
+    sp[0] = make_int2((int)llrint(a.x), (int)llrint(a.y));
+    sw[0] = 1.0 - bt;
+    sp[1] = make_int2((int)llrint(b.x), (int)llrint(b.y));
+    sw[1] = bt;
+    return;
+  }
+  // Voronoi cell of x among the parents and x: bounded (x is strictly inside
+  // the hull) but possibly reaching far out near the hull, so the starting
+  // box grows until no vertex of the cell lies on it
+  double span = 0.0;
+  for (int k = 0; k < np; ++k) span = fmax(span, fmax(fabs(par[k].x - x0), fabs(par[k].y - x1)));
+  GPoly a, b;
+  for (int round = 0; round < 12; ++round) {
+    a.n = 4;
+    a.x[0] = x0 - span; a.y[0] = x1 - span;
+    a.x[1] = x0 + span; a.y[1] = x1 - span;
+    a.x[2] = x0 + span; a.y[2] = x1 + span;
+    a.x[3] = x0 - span; a.y[3] = x1 + span;
+    for (int k = 0; k < np; ++k) {
+      const double p0 = par[k].x, p1 = par[k].y;
+      gclip(a, 2.0 * (p0 - x0), 2.0 * (p1 - x1), p0 * p0 + p1 * p1 - x0 * x0 - x1 * x1, b);
+      a = b;
+    }
+    double reach = 0.0;
+    for (int v = 0; v < a.n; ++v) reach = fmax(reach, fmax(fabs(a.x[v] - x0), fabs(a.y[v] - x1)));
+    if (reach < span * (1.0 - 1e-9)) break;
+    span *= 8.0;
+  }
+  const double total = garea(a);
+  int ns = 0;
+  for (int k = 0; k < np; ++k) {
+    const double p0 = par[k].x, p1 = par[k].y;
+    const double la = 2.0 * (p0 - x0), lb = 2.0 * (p1 - x1), lc = p0 * p0 + p1 * p1 - x0 * x0 - x1 * x1;
+    double reach = -1e300;  // natural neighbour: the cell touches p's bisector with x
+    for (int v = 0; v < a.n; ++v) reach = fmax(reach, la * a.x[v] + lb * a.y[v] - lc);
+    if (reach < -1e-9 * (1.0 + span * span)) continue;
+    GPoly c = a, d;
+    for (int m = 0; m < np && c.n >= 3; ++m) {
+      if (m == k) continue;
+      const double r0 = par[m].x, r1 = par[m].y;
+      gclip(c, 2.0 * (r0 - p0), 2.0 * (r1 - p1), r0 * r0 + r1 * r1 - p0 * p0 - p1 * p1, d);
+      c = d;
+    }
+    const double w = garea(c) / total;
+    if (w > 1e-12) {
+      if (ns == 16) {
+        *overflow = 1;
+        return;
+      }
+      sp[ns] = par[k];
+      sw[ns] = w;
+      ++ns;
+    }
+  }
+}
+
+hipError_t launch_sibson_general(const int2* query, int nq, const int2* parents, int np,
+                                 const double2* hull, int nh, int2* slot_p, double* slot_w,
+                                 int* overflow, hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sibson_general, dim3((nq + 63) / 64), dim3(64), 0, st, query, nq, parents, np,
+                     hull, nh, slot_p, slot_w, overflow);
+  return hipGetLastError();
+}
+
 __global__ void k_zero(float* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
@@ -215,6 +367,17 @@ __global__ void k_zero(float* p, int64_t n) {
 hipError_t launch_zero(float* p, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy(float* out, const float* __restrict__ src, int64_t n, float w, int accumulate) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = accumulate ? out[i] + w * src[i] : w * src[i];
+}
+
+hipError_t launch_axpy(float* out, const float* src, int64_t n, float w, int accumulate, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, src, n, w, accumulate);
   return hipGetLastError();
 }
 

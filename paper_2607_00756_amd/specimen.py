@@ -63,6 +63,10 @@ class Config:
     ionizable_frac: float = 0.0
     vacancy_frac: float = 0.0
     species_b_scale: float = 1.0
+    parents: str = "lattice"      # "lattice" (partition factor s) | "hex" (hex rings)
+    n_radial: int = 4             # hex rings: ring count and angular samples of ring 0
+    n_angular: int = 6
+    focal: bool = False           # focal back-propagation of the S1 parent windows
 
 
 CONFIGS = {
