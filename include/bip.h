@@ -51,7 +51,7 @@ enum {
 
 enum { BIP_RECON_MAGNITUDE = 0, BIP_RECON_COMPLEX = 1 };
 enum { BIP_PARENTS_LATTICE = 0, BIP_PARENTS_HEX = 1 };
-enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2, BIP_OUT_MAP_DIRECT = 3 };
+enum { BIP_OUT_MAP = 0, BIP_OUT_QEELS = 1, BIP_OUT_BEAMS = 2, BIP_OUT_MAP_DIRECT = 3, BIP_OUT_CUBE = 4 };
 enum { BIP_PREC_FP32 = 0, BIP_PREC_SPLIT_BF16 = 1, BIP_PREC_BF16 = 2, BIP_PREC_FP16 = 3 };
 
 typedef struct bip_grid {
@@ -94,6 +94,9 @@ typedef struct bip_optics {
                            and the probe is stepped forward again and cropped to the
                            window; the steps treat the window as periodic.  Forward
                            only (bip_eels_backward returns BIP_EUNSUPPORTED). */
+  int32_t s2_exact;     /* 1: S2 over every detector beam (each its own parent, no
+                           interpolation): the exit side is exact, as Alg. 3 needs for
+                           the energy-filtered 4D cube (BIP_OUT_CUBE) */
 } bip_optics;
 
 typedef struct bip_plan bip_plan;
@@ -193,7 +196,12 @@ int bip_reconstruct_local(bip_plan* plan, int32_t atom, float* s1_out, float* s2
  *                (u N_y/S_y, v N_x/S_x) pixels; output row p = u S_x + v.
  *   out_mode     BIP_OUT_MAP: out f32 [P]; BIP_OUT_QEELS: f32 [P][n_q]
  *                (h_x resolved, bin h_x + floor(theta L_x / lambda));
- *                BIP_OUT_BEAMS: f32 [P][n_det] (detector order of bip_query).
+ *                BIP_OUT_BEAMS: f32 [P][n_det] (detector order of bip_query);
+ *                BIP_OUT_CUBE: f32 [P][n_det], the energy-filtered 4D cube of
+ *                Alg. 3 (eq. cube: partitioned S1, exact exit propagation);
+ *                needs a plan with s2_exact = 1 (else BIP_EINVAL), on which
+ *                the exact detector matrix carries the exit multislice of
+ *                every scan position (eq. s2).
  *   precision    BIP_PREC_FP32 (FP32 MFMA), BIP_PREC_SPLIT_BF16 (hi+lo
  *                bf16 products, FP32 accumulate), BIP_PREC_BF16 or
  *                BIP_PREC_FP16 (one bf16 / fp16 product, FP32 accumulate).

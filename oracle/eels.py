@@ -302,6 +302,8 @@ class BiP:
         else:
             self.part1 = Partition(prob.beams, cfg.partition)
             self.part2 = Partition(prob.det, cfg.partition)
+        if getattr(cfg, "s2_exact", False):
+            self.part2 = Partition(prob.det, 1)  # every detector beam its own parent
         self.recon_mode = recon_mode
         self.focal = bool(getattr(cfg, "focal", False))
 
@@ -400,6 +402,44 @@ class BiP:
                 progress(a)
         out = reduce_output(prob.cfg, I_dp, prob.det, mode)
         return (out, parts) if per_atom else out
+
+
+# -------------------------------------------------------------- Algorithm 3
+def partitioned_cube(prob: Problem, recon_mode=RECON_MAGNITUDE, atoms=None, scans=None):
+    """Alg. 3, the energy-filtered 4D cube I(q, rho) [P, n_det] for q in the
+    detector: the probe from the partitioned S1 (parents, weights,
+    reconstruction and, if configured, focal back-propagation exactly as in
+    Alg. 5), then, per scan position and channel, the inelastic wave
+    H_n psi on the window propagated to the exit by conventional multislice
+    and Fourier-transformed (unitary) to the detector beams (eq. cube)."""
+    cfg = prob.cfg
+    atoms = _atoms(prob, atoms)
+    bip = BiP(prob, recon_mode)
+    pw = bip.parent_windows(atoms)
+    C = illumination(cfg, prob.beams)
+    if scans is not None:
+        C = C[np.asarray(scans)]
+    G = cfg.ny * cfg.nx
+    I = np.zeros((C.shape[0], len(prob.det)))
+    for a in atoms:
+        i = int(prob.planes[a])
+        y, x = prob.window(a)
+        W = len(y)
+        if bip.focal:
+            psi = bip.focal_probe(a, pw[a], C)                     # [K, P]
+        else:
+            s1 = reconstruct(cfg, pw[a][0], bip.part1.parents, bip.part1.W, prob.beams, y, x, 1,
+                             recon_mode)
+            psi = s1.reshape(-1, W * W).T @ C.T
+        Ha = prob.H_atom(a)
+        for p in range(C.shape[0]):
+            for n in range(prob.n_ch):
+                phi = np.zeros((cfg.ny, cfg.nx), np.complex128)
+                phi[y[:, None], x[None, :]] = Ha[n] * psi[:, p].reshape(W, W)
+                phi = ms.exit_operator(phi, prob.T, prob.P, i)
+                amp = (ms.fft2(phi) / math.sqrt(G))[prob.det[:, 0] % cfg.ny, prob.det[:, 1] % cfg.nx]
+                I[p] += amp.real ** 2 + amp.imag ** 2
+    return I
 
 
 # ------------------------------------------------------------- diagnostics

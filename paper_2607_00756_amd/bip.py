@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE = 0, -1, -2, -3, -4, -5
 RECON_MAGNITUDE, RECON_COMPLEX = 0, 1
 PARENTS_LATTICE, PARENTS_HEX = 0, 1
-OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT = 0, 1, 2, 3
+OUT_MAP, OUT_QEELS, OUT_BEAMS, OUT_MAP_DIRECT, OUT_CUBE = 0, 1, 2, 3, 4
 PREC_FP32, PREC_SPLIT_BF16, PREC_BF16, PREC_FP16 = 0, 1, 2, 3
 Q_COUNTS, Q_BEAMS, Q_DETECTOR, Q_PARENTS1, Q_PARENTS2, Q_PLANES, Q_WEIGHTS1, Q_WEIGHTS2, \
     Q_SCALARS, Q_MEMORY = range(10)
@@ -46,7 +46,8 @@ class BipOptics(ctypes.Structure):
                 ("theta_rad", ctypes.c_double), ("partition", ctypes.c_int32),
                 ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32),
                 ("s2_window_gb", ctypes.c_double), ("parent_set", ctypes.c_int32),
-                ("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32), ("focal", ctypes.c_int32)]
+                ("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32), ("focal", ctypes.c_int32),
+                ("s2_exact", ctypes.c_int32)]
 
 
 class BipEdge(ctypes.Structure):
@@ -186,7 +187,7 @@ class Plan:
     def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
                  win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None,
                  allocator="torch", s2_window_gb=0.0, parents="lattice", n_radial=4, n_angular=6,
-                 focal=False):
+                 focal=False, s2_exact=False):
         self._h = _p()
         self._built_key = None
         self.allocator, alloc_ref = _alloc_arg(allocator)
@@ -194,7 +195,7 @@ class Plan:
         self.grid = grid
         opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride, s2_window_gb,
                         {"lattice": PARENTS_LATTICE, "hex": PARENTS_HEX}[parents], n_radial, n_angular,
-                        1 if focal else 0)
+                        1 if focal else 0, 1 if s2_exact else 0)
         tau, tp = _host(tau_xyz, np.float64)
         ws, wp = _host(win_size, np.int32)
         wo, op = _host(win_origin, np.int32)
@@ -212,6 +213,7 @@ class Plan:
         kw.setdefault("n_radial", getattr(cfg, "n_radial", 4))
         kw.setdefault("n_angular", getattr(cfg, "n_angular", 6))
         kw.setdefault("focal", bool(getattr(cfg, "focal", False)))
+        kw.setdefault("s2_exact", bool(getattr(cfg, "s2_exact", False)))
         return cls(cfg.ny, cfg.nx, cfg.nz, cfg.ly, cfg.lx, cfg.dz, cfg.energy_ev, cfg.alpha,
                    cfg.theta, cfg.partition, tau, win_size, win_origin, **kw)
 

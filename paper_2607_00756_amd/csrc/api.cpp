@@ -317,6 +317,7 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   if (o.parent_set == BIP_PARENTS_HEX && (o.n_radial < 1 || o.n_angular < 1))
     return err(BIP_EINVAL, "hex rings need n_radial >= 1 and n_angular >= 1");
   if (o.focal != 0 && o.focal != 1) return err(BIP_EINVAL, "focal must be 0 or 1");
+  if (o.s2_exact != 0 && o.s2_exact != 1) return err(BIP_EINVAL, "s2_exact must be 0 or 1");
   if (o.focal && o.ckpt_stride != 0)
     return err(BIP_EUNSUPPORTED, "focal back-propagation is forward only (ckpt_stride must be 0)");
   if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
@@ -377,6 +378,9 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   } else {
     if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
     if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+  }
+  if (o.s2_exact) {  // every detector beam its own parent: identity weights
+    if ((rc = partition(p, p->det, 1, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
   }
   p->Bp1 = (int)p->par1.size() / 2;
   p->Bp2 = (int)p->par2.size() / 2;
@@ -760,8 +764,13 @@ int bip::signal_edges_impl(bip_plan* p, int32_t n_edges, const bip_edge* edges, 
   if (scan_sy > BIP_MAX_SCAN || scan_sx > BIP_MAX_SCAN)
     return err(BIP_EUNSUPPORTED, "scan raster sides above " + std::to_string(BIP_MAX_SCAN));
   if (out_mode != BIP_OUT_MAP && out_mode != BIP_OUT_QEELS && out_mode != BIP_OUT_BEAMS &&
-      out_mode != BIP_OUT_MAP_DIRECT)
+      out_mode != BIP_OUT_MAP_DIRECT && out_mode != BIP_OUT_CUBE)
     return err(BIP_EINVAL, "unknown out_mode");
+  if (out_mode == BIP_OUT_CUBE) {
+    if (!p->o.s2_exact)
+      return err(BIP_EINVAL, "the 4D cube needs the exact detector matrix (plan with s2_exact = 1)");
+    out_mode = BIP_OUT_BEAMS;  // every detector beam of the exact S2: the cube
+  }
   if (precision != BIP_PREC_FP32 && precision != BIP_PREC_SPLIT_BF16 && precision != BIP_PREC_BF16 &&
       precision != BIP_PREC_FP16)
     return err(BIP_EINVAL, "unknown precision");
@@ -1227,6 +1236,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       q.out_plane = pl2;
       q.tiles = max_n1 / 128;
       q.gscale = 1.f / (gram_scale * gram_scale);
+      q.qtri = 1;
       HIPCHK(timed(p, ST_GRAM, st, [&] {
                return launch_zgemm_gram(gram_prec, precision, q, (int)gemm_gram_blocks(q.tiles, nat), st);
              }),
@@ -1239,6 +1249,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       u.jobs = d_jquad + c0;
       u.njobs = nat;
       u.partial = partial;
+      u.qtri = 1;
       // job groups that fill the chip evenly; partial rows reduced in a fixed order
       const int qt = (int)(Ppad / 128) * (max_n1 / 128);
       u.zsplit = quad_groups(qt, nat, p->n_cu);

@@ -80,6 +80,8 @@ struct GemmArgs {
   const float* rowscale;     // EPI_STORE: optional real factor per output row
   int m_store;               // EPI_STORE: rows >= m_store are not written
   float gscale;              // EPI_GRAMQ: factor on G (undoes a scaling of the operand), > 0
+  int qtri;                  // EPI_GRAMQ: Q block-triangular (upper tiles doubled, lower not
+                             // stored); EPI_QUAD: K from the tile's first column (reads that form)
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {

@@ -392,13 +392,15 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   for (int jb = jb0; jb < jb1; ++jb) {
     const GemmJob job = g.jobs[jb];
     if (n0 >= job.n_lim || m0 >= job.m_lim) continue;  // uniform per workgroup
-    const char* Ap = (const char*)g.A + (job.a_off + (int64_t)m0 * job.lda) * ESZ;
-    const char* Bp = (const char*)g.B + (job.b_off + (int64_t)n0 * job.ldb) * ESZ;
+    // the block-triangular quadratic form runs K over r' >= the tile's first r
+    const int k0 = (EPI == EPI_QUAD && g.qtri) ? n0 : 0;
+    const char* Ap = (const char*)g.A + (job.a_off + (int64_t)m0 * job.lda + k0) * ESZ;
+    const char* Bp = (const char*)g.B + (job.b_off + (int64_t)n0 * job.ldb + k0) * ESZ;
     Acc acc;
     acc.zero();
     const int64_t ch = (job.kstride ? (int64_t)job.kstride : (int64_t)PT<PREC>::BK) * ESZ;
     tile_product<PREC, CONJA>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
-                              (int64_t)job.ldb * ESZ, job.K, ch, smem, wave, lane, wm, wn, acc);
+                              (int64_t)job.ldb * ESZ, job.K - k0, ch, smem, wave, lane, wm, wn, acc);
     if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -478,11 +480,19 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
               qr = cr * hr - ci * hi;
               qi = cr * hi + ci * hr;
             }
-            store_planes<OPREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
-            // Q is Hermitian: the tile below the diagonal is the conjugate transpose
-            if (m0 != n0 && m < job.ldo)
-              store_planes<OPREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
-                                  -qi);
+            if (g.qtri && m0 != n0) {
+              // block-triangular Q for the quadratic form: psi^H Q psi sums each
+              // block pair r < r' twice (Q Hermitian), so the tile above the
+              // diagonal is stored doubled and the one below is never read
+              store_planes<OPREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, 2.f * qr,
+                                  2.f * qi);
+            } else {
+              store_planes<OPREC>(g.out, job.out_off + (int64_t)m * job.ldo + n, g.out_plane, qr, qi);
+              // Q is Hermitian: the tile below the diagonal is the conjugate transpose
+              if (m0 != n0 && m < job.ldo)
+                store_planes<OPREC>(g.out, job.out_off + (int64_t)n * job.ldo + m, g.out_plane, qr,
+                                    -qi);
+            }
             if (g.out2) {  // G itself, for the gradient
               const bool in = m < job.W2 && n < job.W2;
               g.out2[job.out_off + (int64_t)m * job.ldo + n] = in ? make_float2(cr, ci) : make_float2(0.f, 0.f);

@@ -67,6 +67,7 @@ class Config:
     n_radial: int = 4             # hex rings: ring count and angular samples of ring 0
     n_angular: int = 6
     focal: bool = False           # focal back-propagation of the S1 parent windows
+    s2_exact: bool = False        # S2 over every detector beam (the cube of Alg. 3)
 
 
 CONFIGS = {

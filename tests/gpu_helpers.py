@@ -28,7 +28,7 @@ def gpu_run(cfg, V, tau, win_size, win_origin, H, H_off, n_ch, out_mode, precisi
     plan.build_smatrix(Vd)
     P = cfg.scan[0] * cfg.scan[1]
     shape = {bip.OUT_MAP: (P,), bip.OUT_MAP_DIRECT: (P,), bip.OUT_QEELS: (P, plan.nq),
-             bip.OUT_BEAMS: (P, plan.ndet)}[out_mode]
+             bip.OUT_BEAMS: (P, plan.ndet), bip.OUT_CUBE: (P, plan.ndet)}[out_mode]
     out = torch.empty(shape, dtype=torch.float32, device=dev)
     plan.eels_signal(n_ch, Hd, H_off, cfg.scan, out_mode, precision, out, atom_subset=atom_subset)
     torch.cuda.synchronize()

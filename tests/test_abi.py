@@ -67,7 +67,7 @@ def test_allocator_needs_both_callbacks():
     from paper_2607_00756_amd import bip
     half = bip.BipAlloc(bip._ALLOC_FN(lambda n, s, c: None), bip._RELEASE_FN(), None)
     grid = bip.BipGrid(128, 128, 4, 16.0, 16.0, 2.0)
-    opt = bip.BipOptics(200e3, 0.02, 0.04, 4, 0, 0, 0.0, 0, 4, 6, 0)
+    opt = bip.BipOptics(200e3, 0.02, 0.04, 4, 0, 0, 0.0, 0, 4, 6, 0, 0)
     tau = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
     win = (ctypes.c_int32 * 1)(32)
     org = (ctypes.c_int32 * 2)(0, 0)
