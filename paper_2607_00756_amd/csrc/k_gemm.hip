@@ -73,16 +73,28 @@ template <int PREC>
 constexpr int stage_bytes() {
   return 2 * PT<PREC>::PLANES * PLANE_TILE;
 }
-// K chunks in flight: the chunk buffers fill 128 KB of LDS (two 64 KB stages
-// for the four split planes, four 32 KB stages otherwise), so that a chunk's
-// loads have NSTAGE - 1 chunks of matrix work to land
-template <int PREC>
-constexpr int nstage() {
-  return PT<PREC>::PLANES == 4 ? 2 : 4;
+// Workgroups per CU the kernel is built for.  The Gram and plain-store
+// products of two-plane operands run two workgroups (two waves per SIMD, at
+// most 256 registers per lane each), so that one workgroup's barrier and
+// fragment-load waits are covered by the other's matrix work; the other
+// roles keep one, with their larger register sets (running sums, split
+// planes).
+template <int PREC, int EPI>
+constexpr int occupancy() {
+  return (EPI == EPI_GRAMQ || EPI == EPI_STORE) && PT<PREC>::PLANES == 2 ? 2 : 1;
 }
-template <int PREC>
+// K chunks in flight.  One workgroup per CU: the chunk buffers fill 128 KB of
+// LDS (two 64 KB stages for the four split planes, four 32 KB stages
+// otherwise), so that a chunk's loads have NSTAGE - 1 chunks of matrix work
+// to land.  Two per CU: two 32 KB stages each (64 KB), the loads of the next
+// chunk landing under the current chunk's work of both workgroups.
+template <int PREC, int EPI>
+constexpr int nstage() {
+  return occupancy<PREC, EPI>() == 2 ? 2 : (PT<PREC>::PLANES == 4 ? 2 : 4);
+}
+template <int PREC, int EPI>
 constexpr int lds_bytes() {
-  return nstage<PREC>() * stage_bytes<PREC>();
+  return nstage<PREC, EPI>() * stage_bytes<PREC>();
 }
 
 // The quadratic form's epilogue stages the job's psi^T tile [128 rho][128 r]
@@ -98,8 +110,8 @@ constexpr int quad_lds_bytes() {
 }
 template <int PREC, int EPI>
 constexpr int kernel_lds_bytes() {
-  return (EPI == EPI_QUAD && quad_lds_bytes<PREC>() > lds_bytes<PREC>()) ? quad_lds_bytes<PREC>()
-                                                                         : lds_bytes<PREC>();
+  return (EPI == EPI_QUAD && quad_lds_bytes<PREC>() > lds_bytes<PREC, EPI>()) ? quad_lds_bytes<PREC>()
+                                                                              : lds_bytes<PREC, EPI>();
 }
 
 // s_waitcnt vmcnt(N) lgkmcnt(0): this wave's loads older than its last N
@@ -115,11 +127,13 @@ __device__ inline void wait_vm() {
 // The clobber keeps the compiler from moving memory accesses across it.
 __device__ inline void chunk_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// 16-byte slot permutation of LDS row `row`: the rows of one fragment read
-// land on distinct banks whether the LDS serves 8 lanes of 128 bytes or 16
-// lanes of 256 bytes per cycle (rows of equal parity differ in (row/4) mod 4
-// or in bit 1)
-__device__ inline int swz(int row) { return ((row >> 2) ^ (row & 2)) & 3; }
+// 16-byte slot permutation of LDS row `row`.  A 16-byte-per-lane LDS read is
+// served in groups of 8 lanes, 128 bytes per cycle: lanes 0-3 with 20-23,
+// 4-7 with 16-19, 8-11 with 28-31, 12-15 with 24-27 (and the same 32 lanes
+// higher).  With fragment lane l reading row l%16, slot (l/16) ^ swz(row),
+// every group then hits eight distinct 16-byte bank quads; the permutation
+// also keeps 8 or 16 consecutive lanes conflict-free.
+__device__ inline int swz(int row) { return ((row >> 1) & 3) ^ ((row >> 3) & 1); }
 
 template <typename T>
 __device__ inline T neg8(T a) {  // sign flip of eight 16-bit floats (bf16 or fp16)
@@ -296,14 +310,13 @@ __device__ inline void mma_chunk(const char* sA, const char* sB, int wm, int wn,
 // acc = sum over K of A[m0 + .][k] B[n0 + .][k] (A and B point at the tile origins).
 // Chunk kc lives in LDS buffer kc mod NS; the loads of chunks kc+1 .. kc+NS-2
 // may still be in flight while chunk kc is multiplied.
-template <int PREC, bool CONJA>
+template <int PREC, bool CONJA, int NS>
 __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t lda_b, const char* B,
                                     int64_t b_plane_b, int64_t ldb_b, int K, int64_t CH, char* lds,
                                     int wave, int lane, int wm, int wn, Acc& acc) {
   // CH: bytes between consecutive K chunks of a row (64 when K is contiguous)
   constexpr int SB = stage_bytes<PREC>();
   constexpr int OPB = PT<PREC>::PLANES * PLANE_TILE;
-  constexpr int NS = nstage<PREC>();
   constexpr int LPC = 4 * PT<PREC>::PLANES;  // global_load_lds per wave per chunk
   const int nk = K / PT<PREC>::BK;
   auto issue = [&](int kc) {
@@ -333,8 +346,43 @@ __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t ld
 }
 
 // ------------------------------------------------------------- the kernel
+// Upper-triangle tile e of an nt x nt tile grid in blocked order: super-blocks
+// of GS x GS tiles, row-major over the super-blocks with I <= J, row-major
+// inside each (the diagonal ones triangular).  A run of consecutive e then
+// touches few distinct row blocks of the operand.
+constexpr int GS = 8;
+__host__ __device__ inline void blocked_tile(int e, int nt, int& ti, int& tj) {
+  const int ns = (nt + GS - 1) / GS;
+  for (int I = 0; I < ns; ++I) {
+    const int ri = GS < nt - I * GS ? GS : nt - I * GS;
+    for (int J = I; J < ns; ++J) {
+      const int cj = GS < nt - J * GS ? GS : nt - J * GS;
+      const int sz = I == J ? ri * (ri + 1) / 2 : ri * cj;
+      if (e >= sz) {
+        e -= sz;
+        continue;
+      }
+      int i = 0, j;
+      if (I == J) {
+        while (e >= ri - i) {
+          e -= ri - i;
+          ++i;
+        }
+        j = i + e;
+      } else {
+        i = e / cj;
+        j = e - i * cj;
+      }
+      ti = I * GS + i;
+      tj = J * GS + j;
+      return;
+    }
+  }
+  ti = tj = nt;  // not reached for e < nt (nt + 1) / 2
+}
+
 template <int PREC, int EPI, bool CONJA, int OPREC = PREC>
-__global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
+__global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(const GemmArgs g) {
   extern __shared__ char smem[];
   constexpr int ESZ = PT<PREC>::ESZ;
   constexpr bool ACCUM = (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS || EPI == EPI_QUAD);
@@ -345,28 +393,34 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
   if constexpr (EPI == EPI_GRAMQ) {
     // 1-D grid.  Workgroup i runs on XCD i mod 8.  Small jobs (fewer than 64
     // tiles) put all their upper-triangle tiles on one XCD, so the job's
-    // operand rows are shared through its L2; the operand of a large job
-    // outgrows the L2 anyway, and its tiles go to consecutive workgroups so
-    // that a chunk of few large jobs still spreads over every XCD.
+    // operand rows are shared through its L2.  A large job's tiles (padded to
+    // a multiple of 8) are cut into eight contiguous runs of the blocked
+    // order, one per XCD: the tiles an XCD runs at once then share a few
+    // operand row blocks in its L2, and every XCD holds an equal share.
     const int nt = g.tiles, T = nt * (nt + 1) / 2;
-    int tl;
+    int ti, tj;
     if (T < 64) {
       const int slot = (int)(blockIdx.x >> 3);
       jb0 = (slot / T) * 8 + (int)(blockIdx.x & 7);
-      tl = slot % T;
+      int tl = slot % T;
+      ti = 0;
+      while (tl >= nt - ti) {
+        tl -= nt - ti;
+        ++ti;
+      }
+      tj = ti + tl;
     } else {
-      jb0 = (int)blockIdx.x / T;
-      tl = (int)blockIdx.x % T;
+      const int per = (T + 7) / 8;  // tiles per XCD
+      jb0 = (int)(blockIdx.x / (8 * per));
+      const int l = (int)(blockIdx.x % (8 * per));
+      const int e = (l & 7) * per + (l >> 3);
+      if (e >= T) return;  // uniform per workgroup
+      blocked_tile(e, nt, ti, tj);
     }
     if (jb0 >= g.njobs) return;  // uniform per workgroup
     jb1 = jb0 + 1;
-    int ti = 0;
-    while (tl >= nt - ti) {
-      tl -= nt - ti;
-      ++ti;
-    }
     m0 = ti * BM;
-    n0 = (ti + tl) * BN;
+    n0 = tj * BN;
   } else {
     // consecutive workgroups take consecutive M tiles of one N tile
     m0 = blockIdx.x * BM;
@@ -399,7 +453,7 @@ __global__ __launch_bounds__(NTHREADS) void k_zgemm(const GemmArgs g) {
     Acc acc;
     acc.zero();
     const int64_t ch = (job.kstride ? (int64_t)job.kstride : (int64_t)PT<PREC>::BK) * ESZ;
-    tile_product<PREC, CONJA>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
+    tile_product<PREC, CONJA, nstage<PREC, EPI>()>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
                               (int64_t)job.ldb * ESZ, job.K - k0, ch, smem, wave, lane, wm, wn, acc);
     if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
@@ -639,7 +693,9 @@ hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, in
 }
 
 int64_t gemm_gram_blocks(int tiles, int njobs) {
-  return 8 * (int64_t)((njobs + 7) / 8) * (tiles * (tiles + 1) / 2);
+  const int64_t T = (int64_t)tiles * (tiles + 1) / 2;
+  if (T < 64) return 8 * (int64_t)((njobs + 7) / 8) * T;
+  return (int64_t)njobs * 8 * ((T + 7) / 8);
 }
 
 int gemm_bk(int prec) { return prec == BIP_PREC_FP32 ? PT<BIP_PREC_FP32>::BK : 32; }
