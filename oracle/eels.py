@@ -61,16 +61,42 @@ def scan_positions(cfg):
     return np.stack([u.ravel() * cfg.ny / sy, v.ravel() * cfg.nx / sx], axis=1)
 
 
-def illumination(cfg, beams):
-    """c_b(rho) [P, B] = c_b exp(-2 pi i (h_y u / S_y + h_x v / S_x))."""
+def illumination(cfg, beams, n_aperture=None, scale=1.0):
+    """c_b(rho) [P, B] = c_b exp(-2 pi i (h_y u / S_y + h_x v / S_x)).
+
+    c_b = scale / sqrt(G n_aperture), n_aperture the size of the whole
+    aperture (default: the beams given); with PRISM subsampling the retained
+    beams keep the coefficient of the whole aperture times f_y f_x (section
+    "Exact PRISM-EELS", interpolation factor)."""
     sy, sx = cfg.scan
     G = cfg.ny * cfg.nx
-    cb = 1.0 / math.sqrt(G * len(beams))
+    cb = scale / math.sqrt(G * (len(beams) if n_aperture is None else n_aperture))
     u, v = np.meshgrid(np.arange(sy), np.arange(sx), indexing="ij")
     u = u.ravel()[:, None]
     v = v.ravel()[:, None]
     ph = (beams[None, :, 0] * u) / sy + (beams[None, :, 1] * v) / sx
     return cb * np.exp(-2j * math.pi * ph)
+
+
+def prism_subsample(beams, f):
+    """Alg. 2 beam subsampling by the interpolation factor: keep the beams
+    with h_y = 0 and h_x = 0 (mod f)."""
+    beams = np.asarray(beams)
+    keep = (beams[:, 0] % f == 0) & (beams[:, 1] % f == 0)
+    return beams[keep]
+
+
+def crop_mask(cfg, tau, f):
+    """PRISM crop mask of one atom [P] (bool): the scan positions whose
+    f-periodic probe (period N/f) holds the atom inside its alias-free
+    window (section "Exact PRISM-EELS"; the crop mask of Alg. 4).  Reading:
+    the minimum-image displacement atom - rho, in pixels per axis, lies in
+    [-N/(2f), N/(2f)); tau = (x, y, z) in A.  f = 1 keeps every scan."""
+    rho = scan_positions(cfg)                                   # (y, x) pixels
+    t = np.array([tau[1] * cfg.ny / cfg.ly, tau[0] * cfg.nx / cfg.lx])
+    N = np.array([cfg.ny, cfg.nx], dtype=np.float64)
+    d = (t[None, :] - rho + N / 2) % N - N / 2
+    return np.all((d >= -N / (2 * f)) & (d < N / (2 * f)), axis=1)
 
 
 def qeels_bins(cfg):
@@ -286,24 +312,49 @@ def exact_dual(prob: Problem, mode=OUT_MAP, atoms=None, order="probe"):
 
 
 # -------------------------------------------------------------- Algorithm 5
+def _lattice_partition(beams, s, f):
+    """Lattice parents of PRISM-subsampled beams (all multiples of f): the
+    partition of h / f with factor s, parents scaled back by f (Sibson
+    weights are unchanged by the scaling)."""
+    part = Partition(np.asarray(beams) // f, s)
+    part.beams = np.asarray(beams)
+    part.parents = part.parents * f
+    return part
+
+
 class BiP:
-    """Alg. 5: parents, weights, parent sweeps, windowed reconstruction."""
+    """Alg. 5: parents, weights, parent sweeps, windowed reconstruction.
+
+    With the PRISM interpolation factor f = cfg.interp_f > 1 (Alg. 2 and
+    Alg. 4) the aperture and detector beams are subsampled (prism_subsample),
+    the retained illumination coefficients are scaled by f^2, each atom's
+    outputs are kept only on the scans of its crop mask (crop_mask), and the
+    detector sums are scaled by f^2.  Reading for the last point (the paper
+    states the rescaling for the probe side only): by the same decimation
+    argument, a retained detector beam stands for the f x f beams of its
+    cell, which keeps the map on the scale of f = 1 when the inelastic wave
+    fits the alias-free window."""
 
     def __init__(self, prob: Problem, recon_mode=RECON_MAGNITUDE):
         self.prob = prob
         cfg = prob.cfg
+        self.f = f = int(getattr(cfg, "interp_f", 1))
+        if f < 1 or cfg.ny % f or cfg.nx % f:
+            raise ValueError("the interpolation factor must divide the grid")
+        self.beams = prism_subsample(prob.beams, f)
+        self.det = prism_subsample(prob.det, f)
         if getattr(cfg, "parents", "lattice") == "hex":
             # hex-ring parents on the aperture and on the detector disc
             lam = physics.wavelength(cfg.energy_ev)
-            self.part1 = HexPartition(prob.beams, cfg.n_radial, cfg.n_angular,
+            self.part1 = HexPartition(self.beams, cfg.n_radial, cfg.n_angular,
                                       cfg.alpha / lam * cfg.ly, cfg.alpha / lam * cfg.lx)
-            self.part2 = HexPartition(prob.det, cfg.n_radial, cfg.n_angular,
+            self.part2 = HexPartition(self.det, cfg.n_radial, cfg.n_angular,
                                       cfg.theta / lam * cfg.ly, cfg.theta / lam * cfg.lx)
         else:
-            self.part1 = Partition(prob.beams, cfg.partition)
-            self.part2 = Partition(prob.det, cfg.partition)
+            self.part1 = _lattice_partition(self.beams, cfg.partition, f)
+            self.part2 = _lattice_partition(self.det, cfg.partition, f)
         if getattr(cfg, "s2_exact", False):
-            self.part2 = Partition(prob.det, 1)  # every detector beam its own parent
+            self.part2 = Partition(self.det, 1)  # every detector beam its own parent
         self.recon_mode = recon_mode
         self.focal = bool(getattr(cfg, "focal", False))
 
@@ -337,7 +388,7 @@ class BiP:
         M, pad, y, x = focal_window(cfg, W, prob.win_origin[a])
         dist = int(prob.planes[a]) * cfg.dz - centroid_depth(prob, a)
         back = window_fresnel(cfg, pw[0], dist, +1)
-        s1 = reconstruct(cfg, back, self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+        s1 = reconstruct(cfg, back, self.part1.parents, self.part1.W, self.beams, y, x, 1,
                          self.recon_mode)
         psi_c = np.tensordot(C, s1, axes=(1, 0))            # [P, M, M] at the centroid
         psi = window_fresnel(cfg, psi_c, dist, -1)[:, pad:pad + W, pad:pad + W]
@@ -350,11 +401,16 @@ class BiP:
             raise ValueError("focal mode: S1~ exists only at the centroid, on the enlarged window")
         prob = self.prob
         y, x = prob.window(a)
-        s1 = reconstruct(prob.cfg, pw[0], self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+        s1 = reconstruct(prob.cfg, pw[0], self.part1.parents, self.part1.W, self.beams, y, x, 1,
                          self.recon_mode)
-        s2 = reconstruct(prob.cfg, pw[1], self.part2.parents, self.part2.W, prob.det, y, x, 2,
+        s2 = reconstruct(prob.cfg, pw[1], self.part2.parents, self.part2.W, self.det, y, x, 2,
                          self.recon_mode)
         return s1, s2
+
+    def illumination(self):
+        """c_b(rho) [P, B_f] of the retained aperture beams."""
+        return illumination(self.prob.cfg, self.beams, n_aperture=len(self.prob.beams),
+                            scale=float(self.f * self.f))
 
     def run(self, mode=OUT_MAP, atoms=None, order="probe", scans=None, per_atom=False,
             rows=None, progress=None):
@@ -367,11 +423,12 @@ class BiP:
         prob = self.prob
         atoms = _atoms(prob, atoms)
         pw = self.parent_windows(atoms)
-        C = illumination(prob.cfg, prob.beams)
-        if scans is not None:
-            C = C[np.asarray(scans)]
+        C = self.illumination()
+        sel = np.arange(C.shape[0]) if scans is None else np.asarray(scans)
+        C = C[sel]
         contract = contract_probe_order if order == "probe" else contract_m_order
-        I_dp = np.zeros((len(prob.det), C.shape[0]))
+        det = self.det
+        I_dp = np.zeros((len(det), C.shape[0]))
         parts = {}
         for a in atoms:
             psi = self.focal_probe(a, pw[a], C) if self.focal else None
@@ -379,28 +436,32 @@ class BiP:
                 raise ValueError("focal back-propagation acts on the probe: probe order only")
             y, x = prob.window(a)
             s1 = None if psi is not None else \
-                reconstruct(prob.cfg, pw[a][0], self.part1.parents, self.part1.W, prob.beams, y, x, 1,
+                reconstruct(prob.cfg, pw[a][0], self.part1.parents, self.part1.W, self.beams, y, x, 1,
                             self.recon_mode)
             if rows is None:
-                s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W, prob.det, y, x,
+                s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W, det, y, x,
                                  2, self.recon_mode)
                 Ia = contract(s1, s2, prob.H_atom(a), C, psi) if psi is not None else \
                     contract(s1, s2, prob.H_atom(a), C)
             else:
                 Ia = np.zeros_like(I_dp)
-                for d0 in range(0, len(prob.det), rows):
-                    d1 = min(d0 + rows, len(prob.det))
+                for d0 in range(0, len(det), rows):
+                    d1 = min(d0 + rows, len(det))
                     s2 = reconstruct(prob.cfg, pw[a][1], self.part2.parents, self.part2.W[d0:d1],
-                                     prob.det[d0:d1], y, x, 2, self.recon_mode)
+                                     det[d0:d1], y, x, 2, self.recon_mode)
                     Ia[d0:d1] = contract(s1, s2, prob.H_atom(a), C, psi) if psi is not None else \
                         contract(s1, s2, prob.H_atom(a), C)
+            if self.f > 1:
+                # detector sums over retained beams, on the atom's crop mask only
+                Ia = Ia * float(self.f * self.f)
+                Ia[:, ~crop_mask(prob.cfg, prob.tau[a], self.f)[sel]] = 0.0
             if per_atom:
                 parts[a] = Ia
             I_dp += Ia
             pw[a] = None
             if progress:
                 progress(a)
-        out = reduce_output(prob.cfg, I_dp, prob.det, mode)
+        out = reduce_output(prob.cfg, I_dp, det, mode)
         return (out, parts) if per_atom else out
 
 
@@ -415,6 +476,8 @@ def partitioned_cube(prob: Problem, recon_mode=RECON_MAGNITUDE, atoms=None, scan
     cfg = prob.cfg
     atoms = _atoms(prob, atoms)
     bip = BiP(prob, recon_mode)
+    if bip.f != 1:
+        raise ValueError("the 4D cube keeps every exit beam: interpolation factor 1 only")
     pw = bip.parent_windows(atoms)
     C = illumination(cfg, prob.beams)
     if scans is not None:

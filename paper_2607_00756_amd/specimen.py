@@ -68,6 +68,7 @@ class Config:
     n_angular: int = 6
     focal: bool = False           # focal back-propagation of the S1 parent windows
     s2_exact: bool = False        # S2 over every detector beam (the cube of Alg. 3)
+    interp_f: int = 1             # PRISM interpolation factor f (beams kept at h = 0 mod f)
 
 
 CONFIGS = {
