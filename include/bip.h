@@ -97,6 +97,18 @@ typedef struct bip_optics {
   int32_t s2_exact;     /* 1: S2 over every detector beam (each its own parent, no
                            interpolation): the exit side is exact, as Alg. 3 needs for
                            the energy-filtered 4D cube (BIP_OUT_CUBE) */
+  int32_t interp_f;     /* PRISM interpolation factor f (section "Exact PRISM-EELS",
+                           Alg. 2; Alg. 4 for the detector and the crop mask); 0 or 1:
+                           every beam.  f > 1 (dividing ny and nx): only the aperture
+                           and detector beams with h_y = h_x = 0 (mod f) are kept (the
+                           lattice parents sit on the (s f)-lattice), the retained probe
+                           coefficients and the detector sums are scaled by f^2, and an
+                           atom contributes only at the scans of its crop mask: those
+                           whose minimum-image displacement atom - rho (pixels, per
+                           axis) lies in [-N/(2f), N/(2f)), the atom inside the
+                           alias-free window of the N/f-periodic probe.  Forward only
+                           (bip_eels_backward returns BIP_EUNSUPPORTED); not with
+                           s2_exact (BIP_EUNSUPPORTED). */
 } bip_optics;
 
 typedef struct bip_plan bip_plan;

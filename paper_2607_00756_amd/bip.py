@@ -47,7 +47,8 @@ class BipOptics(ctypes.Structure):
                 ("recon_mode", ctypes.c_int32), ("ckpt_stride", ctypes.c_int32),
                 ("s2_window_gb", ctypes.c_double), ("parent_set", ctypes.c_int32),
                 ("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32), ("focal", ctypes.c_int32),
-                ("s2_exact", ctypes.c_int32)]
+                ("s2_exact", ctypes.c_int32),
+                ("interp_f", ctypes.c_int32)]
 
 
 class BipEdge(ctypes.Structure):
@@ -187,7 +188,7 @@ class Plan:
     def __init__(self, ny, nx, nz, ly, lx, dz, energy_ev, alpha, theta, partition, tau_xyz,
                  win_size, win_origin, recon_mode=RECON_MAGNITUDE, ckpt_stride=0, stream=None,
                  allocator="torch", s2_window_gb=0.0, parents="lattice", n_radial=4, n_angular=6,
-                 focal=False, s2_exact=False):
+                 focal=False, s2_exact=False, interp_f=1):
         self._h = _p()
         self._built_key = None
         self.allocator, alloc_ref = _alloc_arg(allocator)
@@ -195,7 +196,7 @@ class Plan:
         self.grid = grid
         opt = BipOptics(energy_ev, alpha, theta, partition, recon_mode, ckpt_stride, s2_window_gb,
                         {"lattice": PARENTS_LATTICE, "hex": PARENTS_HEX}[parents], n_radial, n_angular,
-                        1 if focal else 0, 1 if s2_exact else 0)
+                        1 if focal else 0, 1 if s2_exact else 0, int(interp_f))
         tau, tp = _host(tau_xyz, np.float64)
         ws, wp = _host(win_size, np.int32)
         wo, op = _host(win_origin, np.int32)
@@ -214,6 +215,7 @@ class Plan:
         kw.setdefault("n_angular", getattr(cfg, "n_angular", 6))
         kw.setdefault("focal", bool(getattr(cfg, "focal", False)))
         kw.setdefault("s2_exact", bool(getattr(cfg, "s2_exact", False)))
+        kw.setdefault("interp_f", int(getattr(cfg, "interp_f", 1)))
         return cls(cfg.ny, cfg.nx, cfg.nz, cfg.ly, cfg.lx, cfg.dz, cfg.energy_ev, cfg.alpha,
                    cfg.theta, cfg.partition, tau, win_size, win_origin, **kw)
 

@@ -73,9 +73,39 @@ std::vector<int32_t> beams_within(int ny, int nx, double ly, double lx, double q
 }
 
 // Run the FP64 Sibson kernel on `query` and build the parent set + CSR.
-int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector<int32_t>& parents,
+// Crop mask of one axis (PRISM interpolation factor f): the raster indices u
+// in [0, S) whose minimum-image displacement t - u N / S (pixels) lies in
+// [-N/(2f), N/(2f)), as the cyclic run [start, start + count) mod S (an
+// interval of the circle); f = 1 keeps the whole raster.
+void crop_run(double t, int N, int S, int f, int32_t& start, int32_t& count) {
+  start = 0;
+  count = S;
+  if (f <= 1) return;
+  std::vector<char> in(S);
+  int n = 0;
+  for (int u = 0; u < S; ++u) {
+    double d = t - (double)u * N / S + N / 2.0;
+    d = d - N * std::floor(d / N) - N / 2.0;
+    in[u] = d >= -N / (2.0 * f) && d < N / (2.0 * f);
+    n += in[u];
+  }
+  count = n;
+  if (n == 0 || n == S) return;
+  for (int u = 0; u < S; ++u)
+    if (in[u] && !in[(u + S - 1) % S]) {
+      start = u;
+      break;
+    }
+}
+
+// Lattice partition of `query` (pairs): parents on the (s f)-lattice, weights
+// of the Sibson kernel evaluated on query / f (all query beams are multiples
+// of f; the weights do not change under the scaling).
+int partition(bip_plan* p, const std::vector<int32_t>& query_h, int s, int f, std::vector<int32_t>& parents,
               std::vector<int32_t>& rowptr, std::vector<int32_t>& col, std::vector<double>& w,
               hipStream_t st) {
+  std::vector<int32_t> query(query_h.size());
+  for (size_t i = 0; i < query.size(); ++i) query[i] = query_h[i] / f;
   const int nq = (int)query.size() / 2;
   int2* dq = nullptr;
   int2* dslot = nullptr;
@@ -114,8 +144,8 @@ int partition(bip_plan* p, const std::vector<int32_t>& query, int s, std::vector
   int k = 0;
   for (auto& kv : index) {
     kv.second = k++;
-    parents.push_back(kv.first.first);
-    parents.push_back(kv.first.second);
+    parents.push_back(kv.first.first * f);
+    parents.push_back(kv.first.second * f);
   }
   rowptr.assign(nq + 1, 0);
   col.clear();
@@ -318,6 +348,13 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     return err(BIP_EINVAL, "hex rings need n_radial >= 1 and n_angular >= 1");
   if (o.focal != 0 && o.focal != 1) return err(BIP_EINVAL, "focal must be 0 or 1");
   if (o.s2_exact != 0 && o.s2_exact != 1) return err(BIP_EINVAL, "s2_exact must be 0 or 1");
+  const int fi = o.interp_f == 0 ? 1 : o.interp_f;
+  if (fi < 1 || g.ny % fi != 0 || g.nx % fi != 0)
+    return err(BIP_EINVAL, "interp_f must be >= 1 and divide ny and nx");
+  if (fi > 1 && o.s2_exact)
+    return err(BIP_EUNSUPPORTED, "the exact detector matrix (4D cube) keeps every exit beam: interp_f 1 only");
+  if (fi > 1 && o.ckpt_stride != 0)
+    return err(BIP_EUNSUPPORTED, "interp_f > 1 is forward only (ckpt_stride must be 0)");
   if (o.focal && o.ckpt_stride != 0)
     return err(BIP_EUNSUPPORTED, "focal back-propagation is forward only (ckpt_stride must be 0)");
   if (o.recon_mode != BIP_RECON_MAGNITUDE && o.recon_mode != BIP_RECON_COMPLEX)
@@ -351,6 +388,19 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   p->L = std::max(g.ny, g.nx);
   p->beams = beams_within(g.ny, g.nx, g.ly, g.lx, o.alpha_rad / p->lambda);
   p->det = beams_within(g.ny, g.nx, g.ly, g.lx, o.theta_rad / p->lambda);
+  p->f = fi;
+  p->B_full = (int)p->beams.size() / 2;
+  if (fi > 1) {  // Alg. 2 subsampling of the aperture, and of the detector (Alg. 4)
+    for (auto* set : {&p->beams, &p->det}) {
+      std::vector<int32_t> kept;
+      for (size_t i = 0; i < set->size(); i += 2)
+        if ((*set)[i] % fi == 0 && (*set)[i + 1] % fi == 0) {
+          kept.push_back((*set)[i]);
+          kept.push_back((*set)[i + 1]);
+        }
+      set->swap(kept);
+    }
+  }
   p->B = (int)p->beams.size() / 2;
   p->ndet = (int)p->det.size() / 2;
   const double rq = o.theta_rad / p->lambda * g.lx;
@@ -376,11 +426,11 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
     if ((rc = partition_general(p, p->beams, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
     if ((rc = partition_general(p, p->det, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
   } else {
-    if ((rc = partition(p, p->beams, o.partition, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
-    if ((rc = partition(p, p->det, o.partition, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+    if ((rc = partition(p, p->beams, o.partition, fi, p->par1, p->rp1, p->col1, p->w1, st))) return fail(rc);
+    if ((rc = partition(p, p->det, o.partition, fi, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
   }
   if (o.s2_exact) {  // every detector beam its own parent: identity weights
-    if ((rc = partition(p, p->det, 1, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
+    if ((rc = partition(p, p->det, 1, 1, p->par2, p->rp2, p->col2, p->w2, st))) return fail(rc);
   }
   p->Bp1 = (int)p->par1.size() / 2;
   p->Bp2 = (int)p->par2.size() / 2;
@@ -407,9 +457,13 @@ int bip_plan_create(const bip_grid* grid, const bip_optics* optics, int32_t n_at
   p->W1.resize(n_atoms);
   p->oy1.resize(n_atoms);
   p->ox1.resize(n_atoms);
+  p->tau_y.resize(n_atoms);
+  p->tau_x.resize(n_atoms);
   for (int a = 0; a < n_atoms; ++a) {
     const int W = win_size[a];
     p->W[a] = W;
+    p->tau_y[a] = tau_xyz[3 * a + 1] * g.ny / g.ly;
+    p->tau_x[a] = tau_xyz[3 * a] * g.nx / g.lx;
     p->oy[a] = ((win_origin[2 * a] % g.ny) + g.ny) % g.ny;
     p->ox[a] = ((win_origin[2 * a + 1] % g.nx) + g.nx) % g.nx;
     // S1 window: the enlarged M x M one (M the smallest power of two >= 2W),
@@ -1030,6 +1084,9 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     const int a = atoms[i];
     const int W = p->W[a];
     const int32_t W2 = W * W, kd = (int32_t)kd_of(W);
+    int32_t cu0, cnu, cv0, cnv;
+    crop_run(p->tau_y[a], p->g.ny, scan_sy, p->f, cu0, cnu);
+    crop_run(p->tau_x[a], p->g.nx, scan_sx, p->f, cv0, cnv);
     ProbeJob pj{};
     pj.win_off = p->off1[a];
     pj.fx_off = off[0][i];
@@ -1074,6 +1131,10 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       u.m_lim = (int32_t)Ppad;
       u.n_lim = W2;
       u.W2 = W2;
+      u.cu0 = cu0;
+      u.cnu = cnu;
+      u.cv0 = cv0;
+      u.cnv = cnv;
       jquad.push_back(u);
     } else {
       for (int n = 0; n < n_ch; ++n) {
@@ -1085,6 +1146,10 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
         d.m_lim = (int32_t)Dpad;
         d.n_lim = (int32_t)Ppad;
         d.W2 = W2;
+        d.cu0 = cu0;
+        d.cnu = cnu;
+        d.cv0 = cv0;
+        d.cnv = cnv;
         jdet.push_back(d);
       }
     }
@@ -1131,7 +1196,8 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   pa.Sx = scan_sx;
   pa.P = P;
   pa.Ppad = (int)Ppad;
-  pa.cb = (float)(1.0 / std::sqrt((double)p->g.ny * p->g.nx * p->B));
+  // probe coefficients of the whole aperture; retained beams scaled by f^2
+  pa.cb = (float)((double)p->f * p->f / std::sqrt((double)p->g.ny * p->g.nx * p->B_full));
   pa.H = (const float2*)H;
   pa.n_ch = n_ch;
   for (size_t c = 0; c < chunks.size(); ++c) {
@@ -1224,6 +1290,11 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     g.ndet = p->ndet;
     g.P = P;
     g.Mpad = (int)Ppad;
+    // PRISM interpolation factor: crop masks and the f^2 of the detector sum
+    g.crop = p->f > 1 ? 1 : 0;
+    g.Sy = scan_sy;
+    g.Sx = scan_sx;
+    g.oscale = (float)(p->f * p->f);
     if (gram) {
       GemmArgs q = g;
       q.A = S2op;
@@ -1235,7 +1306,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       q.out = X2;
       q.out_plane = pl2;
       q.tiles = max_n1 / 128;
-      q.gscale = 1.f / (gram_scale * gram_scale);
+      q.gscale = (float)(p->f * p->f) / (gram_scale * gram_scale);
       q.qtri = 1;
       HIPCHK(timed(p, ST_GRAM, st, [&] {
                return launch_zgemm_gram(gram_prec, precision, q, (int)gemm_gram_blocks(q.tiles, nat), st);

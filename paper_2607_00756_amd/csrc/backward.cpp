@@ -55,6 +55,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
                       float* dL_dHconj, const float* dHdx, const float* dHdy, double* dL_dtau_xy,
                       void* stream) {
   if (!p || !H || !H_off || !dL_dI || !dL_dV) return err(BIP_EINVAL, "NULL argument");
+  if (p->f > 1) return err(BIP_EUNSUPPORTED, "interp_f > 1 is forward only");
   if (!p->built) return err(BIP_ESTATE, "bip_build_smatrix has not run");
   if (!p->d_ckpt2) return err(BIP_ESTATE, "plan created without slice checkpoints (ckpt_stride 0)");
   if (p->focal) return err(BIP_EUNSUPPORTED, "focal back-propagation is forward only");

@@ -48,6 +48,8 @@ struct GemmJob {
   int32_t W2;            // window pixels of the atom
   int32_t kstride;       // elements between consecutive 64-byte K chunks of a row of A and
                          // B (0: contiguous; K-blocked operands: row count x chunk width)
+  int32_t cu0, cnu;      // crop mask of the atom (GemmArgs::crop): raster rows u with
+  int32_t cv0, cnv;      // (u - cu0) mod S_y < cnu and columns v with (v - cv0) mod S_x < cnv
 };
 
 // One atom of a batched K-blocked operand reconstruction.
@@ -82,6 +84,9 @@ struct GemmArgs {
   float gscale;              // EPI_GRAMQ: factor on G (undoes a scaling of the operand), > 0
   int qtri;                  // EPI_GRAMQ: Q block-triangular (upper tiles doubled, lower not
                              // stored); EPI_QUAD: K from the tile's first column (reads that form)
+  int crop;                  // EPI_ABS2_*, EPI_QUAD: keep scan rho = u S_x + v only inside the
+  int Sy, Sx;                // job's crop mask (PRISM interpolation factor > 1)
+  float oscale;              // EPI_ABS2_*: factor on the intensities (f^2 of the detector sum)
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {
@@ -159,6 +164,9 @@ struct bip_plan {
   std::vector<int32_t> rp1, col1, rp2, col2;    // CSR of w(1), w(2)
   std::vector<double> w1, w2;
   int B = 0, ndet = 0, Bp1 = 0, Bp2 = 0, nq = 0, nq_half = 0;
+  int f = 1;           // PRISM interpolation factor (beams kept at h = 0 mod f)
+  int B_full = 0;      // aperture beams before the subsampling (probe normalization)
+  std::vector<double> tau_y, tau_x;  // atom positions (pixels), for the crop mask
   // atoms
   int n_atoms = 0;
   std::vector<int32_t> W, oy, ox, plane;

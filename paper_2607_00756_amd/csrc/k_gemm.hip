@@ -346,6 +346,21 @@ __device__ inline void tile_product(const char* A, int64_t a_plane_b, int64_t ld
 }
 
 // ------------------------------------------------------------- the kernel
+// Crop mask of a job (PRISM interpolation factor > 1): scan rho = u S_x + v
+// is kept when (u - cu0) mod S_y < cnu and (v - cv0) mod S_x < cnv.
+__device__ inline bool crop_in(const GemmJob& j, int rho, int Sy, int Sx) {
+  const int u = rho / Sx, v = rho - u * Sx;
+  return (u - j.cu0 + Sy) % Sy < j.cnu && (v - j.cv0 + Sx) % Sx < j.cnv;
+}
+// Whether any raster row of the scans rho0 .. rho1 is inside the job's crop
+// rows (uniform per workgroup: a tile with none skips the job).
+__device__ inline bool crop_rows_any(const GemmJob& j, int rho0, int rho1, int Sy, int Sx) {
+  if (j.cnu <= 0 || j.cnv <= 0) return false;
+  for (int u = rho0 / Sx; u <= rho1 / Sx && u < Sy; ++u)
+    if ((u - j.cu0 + Sy) % Sy < j.cnu) return true;
+  return false;
+}
+
 // Upper-triangle tile e of an nt x nt tile grid in blocked order: super-blocks
 // of GS x GS tiles, row-major over the super-blocks with I <= J, row-major
 // inside each (the diagonal ones triangular).  A run of consecutive e then
@@ -446,6 +461,12 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
   for (int jb = jb0; jb < jb1; ++jb) {
     const GemmJob job = g.jobs[jb];
     if (n0 >= job.n_lim || m0 >= job.m_lim) continue;  // uniform per workgroup
+    if constexpr (EPI == EPI_QUAD || EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
+      // scans along M (quadratic form) or N (detector products); a tile
+      // holding no row of the job's crop mask skips the job
+      const int s0 = EPI == EPI_QUAD ? m0 : n0;
+      if (g.crop && !crop_rows_any(job, s0, min(s0 + 127, g.P - 1), g.Sy, g.Sx)) continue;
+    }
     // the block-triangular quadratic form runs K over r' >= the tile's first r
     const int k0 = (EPI == EPI_QUAD && g.qtri) ? n0 : 0;
     const char* Ap = (const char*)g.A + (job.a_off + (int64_t)m0 * job.lda + k0) * ESZ;
@@ -457,10 +478,13 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
                               (int64_t)job.ldb * ESZ, job.K - k0, ch, smem, wave, lane, wm, wn, acc);
     if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        // column n = scan rho of this lane's block j
+        const bool keep = !g.crop || crop_in(job, n0 + wn * 64 + j * 16 + lr, g.Sy, g.Sx);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          sq[i][j] += acc.re[i][j] * acc.re[i][j] + acc.im[i][j] * acc.im[i][j];
+        for (int i = 0; i < 4; ++i)
+          if (keep) sq[i][j] += acc.re[i][j] * acc.re[i][j] + acc.im[i][j] * acc.im[i][j];
+      }
     } else if constexpr (EPI == EPI_QUAD) {
       // Re conj(psi^T[rho][r]) (Q psi)^T[rho][r]; psi is read back from the A
       // operand: the tile's rows m0.. and columns n0.. (columns below the
@@ -488,6 +512,7 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rhol = wm * 64 + bm * 16 + kg * 4 + v;  // rho - m0
+            if (g.crop && !crop_in(job, m0 + rhol, g.Sy, g.Sx)) continue;
             const float2 ps = load_planes<PREC>(smem, (int64_t)rhol * QR + rl, QPL);
             sq[bm][bn][v] += ps.x * acc.re[bm][bn][v] + ps.y * acc.im[bm][bn][v];
           }
@@ -577,7 +602,7 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
         for (int bn = 0; bn < 4; ++bn) red[wm][wn * 64 + bn * 16 + lr] = cs[bn];
       }
       __syncthreads();
-      if (tid < BN) g.partial[(int64_t)blockIdx.x * g.Npad + n0 + tid] = red[0][tid] + red[1][tid];
+      if (tid < BN) g.partial[(int64_t)blockIdx.x * g.Npad + n0 + tid] = g.oscale * (red[0][tid] + red[1][tid]);
     } else {
       // rows rho = m0 + 64 wm + 16 bm + 4 kg + v; sum over r (lanes lr, blocks bn, waves wn)
 #pragma unroll
@@ -606,7 +631,7 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int d = m0 + wm * 64 + bm * 16 + kg * 4 + v;
-          if (d < g.ndet) g.out_beams[(int64_t)rho * g.ndet + d] += sq[bm][bn][v];
+          if (d < g.ndet) g.out_beams[(int64_t)rho * g.ndet + d] += g.oscale * sq[bm][bn][v];
         }
     }
   }
