@@ -35,6 +35,11 @@ HBM_PEAK_GBS = 8000.0
 PREC = {"fp32": 0, "split": 1, "bf16": 2, "fp16": 3}
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,8 +228,10 @@ def full_map_leg(precision="split", steps=1, warmup=1):
 
     dev = torch.device("cuda:0")
     t_setup = time.perf_counter()
+    log("full-map workload: building the specimen")
     sp = specimen.make(2)
     cfg = sp.cfg
+    log("full-map workload: plan")
     plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin)
     V = torch.from_numpy(sp.V).to(dev)
     H = torch.from_numpy(sp.H).to(dev)
@@ -237,8 +244,10 @@ def full_map_leg(precision="split", steps=1, warmup=1):
         plan.build_smatrix(V)
         plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, prec, out)
 
-    for _ in range(warmup):
+    for i in range(warmup):
         step()
+        torch.cuda.synchronize()
+        log(f"full-map workload: warmup step {i + 1} done")
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -260,6 +269,48 @@ def full_map_leg(precision="split", steps=1, warmup=1):
            "B": plan.B, "n_det": plan.ndet, "Bp1": plan.Bp1, "Bp2": plan.Bp2,
            "s2_plane_segments": int(sc[3]), "plan_device_GB": float(mem[1]) / 1e9,
            "setup_s": t_setup, "map_sum": float(out.double().sum().item())}
+    plan.close()
+    return res
+
+
+def prism_f_leg(precision="split", f=4, steps=3, warmup=1):
+    """The medium workload at PRISM interpolation factor f (the paper's
+    production setting; the benchmark itself is f = 1): aperture and detector
+    beams on the f-lattice, each atom evaluated on the scans of its crop mask
+    (P / f^2 of them).  Timed steps of build + signal (HIP events)."""
+    import dataclasses
+    import torch
+    from paper_2607_00756_amd import bip, specimen
+
+    dev = torch.device("cuda:0")
+    sp = specimen.make(1)
+    cfg = dataclasses.replace(sp.cfg, interp_f=f)
+    plan = bip.Plan.from_config(cfg, sp.tau, sp.win_size, sp.win_origin)
+    V = torch.from_numpy(sp.V).to(dev)
+    H = torch.from_numpy(sp.H).to(dev)
+    P = cfg.scan[0] * cfg.scan[1]
+    out = torch.empty(P, dtype=torch.float32, device=dev)
+
+    def step():
+        plan.build_smatrix(V)
+        plan.eels_signal(sp.n_ch, H, sp.H_off, cfg.scan, bip.OUT_MAP, PREC[precision], out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": f"{cfg.name} at interpolation factor f={f}: {len(sp.tau)} atoms x {sp.n_ch} "
+                       f"channels, scan {cfg.scan[0]}x{cfg.scan[1]}, map; each atom on its crop mask "
+                       f"({P // (f * f)} of {P} scans)",
+           "ms_per_step": ms, "steps": steps, "precision": precision, "B": plan.B, "n_det": plan.ndet,
+           "Bp1": plan.Bp1, "Bp2": plan.Bp2,
+           "evaluated_units_per_s": P // (f * f) * len(sp.tau) * sp.n_ch / (ms / 1e3)}
     plan.close()
     return res
 
@@ -528,11 +579,16 @@ def main():
         res["other_precisions"] = other
     plan.close()
     del plan, V, H, out
+    log(f"benchmark workload done: {ms_step:.2f} ms per step")
     if not args.no_grad:
+        log("gradient leg")
         res["gradient"] = gradient_leg(args.steps, args.warmup)
     if not args.no_fullmap and args.config == 1 and args.atoms is None:
+        log("interpolation-factor leg")
+        res["prism_f4"] = prism_f_leg(args.precision)
         res["full_map_workload"] = full_map_leg(args.precision)
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(sp)
     print(json.dumps(res))
 

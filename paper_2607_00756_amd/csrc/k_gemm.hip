@@ -406,17 +406,20 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
   const int lr = lane & 15, kg = lane >> 4;
   int m0, n0, jb0, jb1;
   if constexpr (EPI == EPI_GRAMQ) {
-    // 1-D grid.  Workgroup i runs on XCD i mod 8.  Small jobs (fewer than 64
-    // tiles) put all their upper-triangle tiles on one XCD, so the job's
-    // operand rows are shared through its L2.  A large job's tiles (padded to
-    // a multiple of 8) are cut into eight contiguous runs of the blocked
-    // order, one per XCD: the tiles an XCD runs at once then share a few
-    // operand row blocks in its L2, and every XCD holds an equal share.
+    // 1-D grid.  Workgroup i runs on XCD i mod 8.  When every job of the
+    // launch has fewer than 64 tiles, all the upper-triangle tiles of a job
+    // go to one XCD, so the job's operand rows are shared through its L2.
+    // Otherwise each job's own tiles (ceil(W^2 / 128) per side) are cut into
+    // eight equal contiguous runs of the blocked order, one per XCD: the
+    // tiles an XCD runs at once then share a few operand row blocks in its
+    // L2, and every XCD holds an equal share of every job, whatever the
+    // window sizes mixed in the launch.
     const int nt = g.tiles, T = nt * (nt + 1) / 2;
     int ti, tj;
     if (T < 64) {
       const int slot = (int)(blockIdx.x >> 3);
       jb0 = (slot / T) * 8 + (int)(blockIdx.x & 7);
+      if (jb0 >= g.njobs) return;  // uniform per workgroup
       int tl = slot % T;
       ti = 0;
       while (tl >= nt - ti) {
@@ -425,14 +428,16 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
       }
       tj = ti + tl;
     } else {
-      const int per = (T + 7) / 8;  // tiles per XCD
+      const int per = (T + 7) / 8;  // slots per XCD and job
       jb0 = (int)(blockIdx.x / (8 * per));
+      if (jb0 >= g.njobs) return;  // uniform per workgroup
+      const int ntj = (g.jobs[jb0].n_lim + BN - 1) / BN, Tj = ntj * (ntj + 1) / 2;
+      const int perj = (Tj + 7) / 8;
       const int l = (int)(blockIdx.x % (8 * per));
-      const int e = (l & 7) * per + (l >> 3);
-      if (e >= T) return;  // uniform per workgroup
-      blocked_tile(e, nt, ti, tj);
+      const int e = (l & 7) * perj + (l >> 3);
+      if ((l >> 3) >= perj || e >= Tj) return;  // uniform per workgroup
+      blocked_tile(e, ntj, ti, tj);
     }
-    if (jb0 >= g.njobs) return;  // uniform per workgroup
     jb1 = jb0 + 1;
     m0 = ti * BM;
     n0 = tj * BN;
