@@ -393,7 +393,7 @@ def atom_groups_run(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

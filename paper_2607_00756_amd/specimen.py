@@ -71,7 +71,7 @@ class Config:
     interp_f: int = 1             # PRISM interpolation factor f (beams kept at h = 0 mod f)
 
 
-CONFIGS = {
+WORKLOADS = {
     0: Config("c0-tiny", 128, 128, 10, 16.0, 16.0, 2.0, 200e3, 20e-3, 40e-3, 4, (16, 16),
               "sc", 4.0, 20.0, 1.0, 0.08, "l1", 32, "nearest_centre"),
     1: Config("c1-medium", 256, 256, 50, 40.0, 40.0, 2.0, 300e3, 25e-3, 50e-3, 4, (64, 64),
@@ -261,7 +261,7 @@ def make(cfg_id: int, cfg: Optional[Config] = None, n_ionized: Optional[int] = N
     cfg may override the geometry (tests shrink grids); positions_override
     replaces the displaced positions (gradient targets); win_origin_override
     pins the windows (held at the unperturbed origins)."""
-    cfg = cfg or CONFIGS[cfg_id]
+    cfg = cfg or WORKLOADS[cfg_id]
     nominal, col = _sites(cfg)
     n = nominal.shape[0]
     r_species = rng(cfg_id, 1)
@@ -339,4 +339,4 @@ def make(cfg_id: int, cfg: Optional[Config] = None, n_ionized: Optional[int] = N
 
 def shrink(cfg_id: int, **kw) -> Config:
     """A copy of a configuration with some fields replaced (small test cases)."""
-    return dataclasses.replace(CONFIGS[cfg_id], **kw)
+    return dataclasses.replace(WORKLOADS[cfg_id], **kw)

@@ -13,7 +13,7 @@ from paper_2607_00756_amd import specimen
 
 def tiny_cfg(ny=16, nx=16, nz=3, ly=4.0, lx=4.0, dz=2.0, energy=200e3, alpha=20e-3,
              theta=40e-3, s=1, scan=(4, 4)):
-    return dataclasses.replace(specimen.CONFIGS[0], name="tiny", ny=ny, nx=nx, nz=nz, ly=ly, lx=lx,
+    return dataclasses.replace(specimen.WORKLOADS[0], name="tiny", ny=ny, nx=nx, nz=nz, ly=ly, lx=lx,
                                dz=dz, energy_ev=energy, alpha=alpha, theta=theta, partition=s,
                                scan=scan)
 

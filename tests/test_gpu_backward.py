@@ -3,7 +3,7 @@
 Parity with the FP64 oracle gradient (oracle/adjoint.py, itself pinned by
 central differences) on ragged problems, both reconstruction modes, with and
 without column batching of the reverse sweeps; and central differences of
-the GPU's own forward map at the full gradient configuration (config 4).
+the GPU's own forward map at the full size of the differentiation workload (256^2, 30 slices, 16 atoms x 3).
 Both sides take the same dL/dI = 2 (I - I_t) from the oracle's map, so the
 comparison isolates the backward.  Bar: rel-L2 <= 1e-3."""
 from __future__ import annotations

@@ -1,4 +1,4 @@
-"""Parity at the full size of the benchmark workload (config 1: 256^2 grid,
+"""Parity at the full size of the benchmark workload (medium workload: 256^2 grid,
 50 slices, 112 atoms x 9 channels, 64 x 64 scan), in the launch configuration
 bench.py times: the plan holds every atom, the contraction runs for a sample
 of atoms (those ionized in the deepest plane, which keeps the oracle's parent

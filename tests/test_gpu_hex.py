@@ -57,7 +57,7 @@ def test_hex_weights_full_size_sampled():
     set against the oracle's general construction."""
     from paper_2607_00756_amd import bip
     torch_dev()
-    cfg = dataclasses.replace(specimen.CONFIGS[1], parents="hex", n_radial=4, n_angular=6)
+    cfg = dataclasses.replace(specimen.WORKLOADS[1], parents="hex", n_radial=4, n_angular=6)
     plan = bip.Plan.from_config(cfg, [[20.0, 20.0, 50.0]], [24], [[116, 116]])
     lam = ph.wavelength(cfg.energy_ev)
     r = np.random.default_rng(9)

@@ -33,7 +33,7 @@ def _bip():
 # ------------------------------------------------------------------ geometry
 @pytest.mark.parametrize("cfg_id", [0, 1, 2, 3, 4])
 def test_beams_parents_and_sibson_weights(cfg_id):
-    cfg = specimen.CONFIGS[cfg_id]
+    cfg = specimen.WORKLOADS[cfg_id]
     print(f"[geometry] config {cfg_id}", flush=True)
     plan = make_plan(cfg, [[1.0, 1.0, 1.0]], [8], [[0, 0]])
     beams, det = ph.aperture_beams(cfg), ph.detector_beams(cfg)
@@ -54,7 +54,7 @@ def test_beams_parents_and_sibson_weights(cfg_id):
     plan.close()
 
 
-# --------------------------------------------------------------- config 0
+# ------------------------------------------------ tiny workload (128^2)
 @pytest.fixture(scope="module")
 def c0():
     sp = specimen.make(0)

@@ -50,9 +50,10 @@ def _disc_count(r2: float) -> int:
     return sum(_two_square_count(n) for n in range(int(math.floor(r2)) + 1))
 
 
-# Appendix A of the build survey, computed there by a separate script from
-# the same readings (inclusive disc, lattice parents with a Sibson weight).
-APPENDIX_A = {  # config: (B, n_det, B_p1, B_p2)
+# Beam and parent counts of the five workloads, computed independently by a
+# separate enumeration with the same readings (inclusive disc, lattice parents
+# with a Sibson weight).
+APPENDIX_A = {  # workload: (B, n_det, B_p1, B_p2)
     0: (509, 2053, 61, 177),
     1: (8093, 32417, 601, 2233),
     2: (46677, 186693, 1481, 5513),
@@ -67,7 +68,7 @@ def test_beam_counts_against_two_square_theorem(cid):
     cell are discs of radius R = angle L / lambda in beam-index units (forward
     model, "Grid, probe and specimen"; q = h / L); their sizes follow from
     Jacobi's r2(n) independently of how the oracle enumerates beams."""
-    cfg = specimen.CONFIGS[cid]
+    cfg = specimen.WORKLOADS[cid]
     assert cfg.ly == cfg.lx and cfg.ny == cfg.nx
     lam = ph.wavelength(cfg.energy_ev)
     for angle, beams in ((cfg.alpha, ph.aperture_beams(cfg)), (cfg.theta, ph.detector_beams(cfg))):
@@ -131,9 +132,8 @@ def test_gaussian_beam_spreads_as_continuous_fresnel_integral():
 def test_propagator_corner_phase(cid, corner_rad):
     """The largest Fresnel phase pi lambda dz |q|^2 sits at the grid corner
     h = (-N/2, -N/2): about 5.0 rad on the 128^2 workload and 22.9 rad on the
-    1024^2 one (build survey, propagator row), which is why the phase table is
-    built in FP64."""
-    cfg = specimen.CONFIGS[cid]
+    1024^2 one, which is why the phase table is built in FP64."""
+    cfg = specimen.WORKLOADS[cid]
     P = ph.propagator(cfg)
     lam = ph.wavelength(cfg.energy_ev)
     q2 = (cfg.ny / 2 / cfg.ly) ** 2 + (cfg.nx / 2 / cfg.lx) ** 2
@@ -196,7 +196,7 @@ def test_projected_potential_poisson_sums(cid):
     So sum_r V cos(2 pi k x / L_x) is known in closed form, and so is its
     derivative with respect to x_a, which potential_grad must return for the
     cotangent dL/dV = cos(2 pi k x / L_x)."""
-    cfg = specimen.CONFIGS[cid]
+    cfg = specimen.WORKLOADS[cid]
     amps = np.array([specimen.POT_AMPS, [2 * a for a in specimen.POT_AMPS]])
     widths = np.array(specimen.POT_WIDTHS)
     xyz = np.array([[3.3, 7.1, 1.0], [cfg.lx - 0.2, 0.3, 1.5 * cfg.dz]])
