@@ -71,6 +71,9 @@ def parse():
                     help="context run: split the ionized atoms into K groups, each with a plan of "
                          "its own that sweeps the parents once for its atoms (a workload whose "
                          "window stacks do not fit one plan), maps summed over the groups")
+    ap.add_argument("--no-stage-events", action="store_true",
+                    help="context runs: time the steps only (no second pass with HIP events around "
+                         "every launch, so no per-stage times or rooflines in the output)")
     ap.add_argument("--no-fullmap", action="store_true",
                     help="skip the full-map workload leg (512^2, 100 slices, 2000 atoms x 3)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -448,6 +451,17 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    if args.no_stage_events:
+        units = P * len(sp.tau) * sp.n_ch
+        print(json.dumps({"metric": f"scan-positions*transitions/s ({args.output})", "value": units / (ms_step / 1e3),
+                          "unit": "scan-positions*transitions/s", "ms_per_step": ms_step, "steps": args.steps,
+                          "warmup": args.warmup, "precision": args.precision,
+                          "config": {"workload": f"{cfg.name}: {len(sp.tau)} atoms x {sp.n_ch} channels, "
+                                                 f"{cfg.ny}^2 grid, {cfg.nz} slices, scan {cfg.scan[0]}x{cfg.scan[1]}, "
+                                                 f"{args.output}", "B": plan.B, "n_det": plan.ndet,
+                                     "Bp1": plan.Bp1, "Bp2": plan.Bp2}}))
+        plan.close()
+        return
     # the same number of steps again with HIP events around every launch, on
     # the launch stream, for the per-stage times and the kernel rooflines
     plan.set_profiling(True)

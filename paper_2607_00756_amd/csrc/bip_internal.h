@@ -87,6 +87,7 @@ struct GemmArgs {
   int crop;                  // EPI_ABS2_*, EPI_QUAD: keep scan rho = u S_x + v only inside the
   int Sy, Sx;                // job's crop mask (PRISM interpolation factor > 1)
   float oscale;              // EPI_ABS2_*: factor on the intensities (f^2 of the detector sum)
+  int mtiles, ntiles;        // EPI_ABS2_*: output tiles along M and N (set by launch_zgemm)
 };
 // One atom of the probe synthesis (offsets in elements of their buffers).
 struct ProbeJob {
