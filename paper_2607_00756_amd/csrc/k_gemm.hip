@@ -81,8 +81,19 @@ constexpr int stage_bytes() {
 // planes).
 template <int PREC, int EPI>
 constexpr int occupancy() {
-  return (EPI == EPI_GRAMQ || EPI == EPI_STORE) && PT<PREC>::PLANES == 2 ? 2 : 1;
+  return (EPI == EPI_GRAMQ || EPI == EPI_STORE) && PT<PREC>::PLANES == 2 && PREC != BIP_PREC_FP32 ? 2 : 1;
 }
+// The FP32 Gram matrix sums its K products (all detector beams) in segments
+// of KSEG: each segment in its own accumulators, added to a running total.
+// v_mfma_f32_16x16x4f32 rounds the accumulator every 4 products, so an
+// unsegmented sum over 10^5 beams rounds ~5*10^4 times per element; the
+// segments bound that to KSEG/4 + K/KSEG.  (The 16-bit products accumulate
+// 32 products per rounding and are not segmented.)
+template <int PREC, int EPI>
+constexpr bool k_segmented() {
+  return EPI == EPI_GRAMQ && PREC == BIP_PREC_FP32;
+}
+constexpr int KSEG = 2048;
 // K chunks in flight.  One workgroup per CU: the chunk buffers fill 128 KB of
 // LDS (two 64 KB stages for the four split planes, four 32 KB stages
 // otherwise), so that a chunk's loads have NSTAGE - 1 chunks of matrix work
@@ -497,8 +508,28 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
     Acc acc;
     acc.zero();
     const int64_t ch = (job.kstride ? (int64_t)job.kstride : (int64_t)PT<PREC>::BK) * ESZ;
-    tile_product<PREC, CONJA, nstage<PREC, EPI>()>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp, g.b_plane * ESZ,
-                              (int64_t)job.ldb * ESZ, job.K - k0, ch, smem, wave, lane, wm, wn, acc);
+    if constexpr (k_segmented<PREC, EPI>()) {
+      Acc seg;
+      for (int ks = 0; ks < job.K - k0; ks += KSEG) {
+        seg.zero();
+        const int64_t koff = (int64_t)(ks / PT<PREC>::BK) * ch;  // K chunks of the segment's start
+        tile_product<PREC, CONJA, nstage<PREC, EPI>()>(Ap + koff, g.a_plane * ESZ, (int64_t)job.lda * ESZ,
+                                                       Bp + koff, g.b_plane * ESZ, (int64_t)job.ldb * ESZ,
+                                                       min(KSEG, job.K - k0 - ks), ch, smem, wave, lane, wm,
+                                                       wn, seg);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc.re[i][j] += seg.re[i][j];
+            acc.im[i][j] += seg.im[i][j];
+          }
+      }
+    } else {
+      tile_product<PREC, CONJA, nstage<PREC, EPI>()>(Ap, g.a_plane * ESZ, (int64_t)job.lda * ESZ, Bp,
+                                                     g.b_plane * ESZ, (int64_t)job.ldb * ESZ, job.K - k0, ch,
+                                                     smem, wave, lane, wm, wn, acc);
+    }
     if constexpr (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
