@@ -416,7 +416,9 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
   extern __shared__ char smem[];
   constexpr int ESZ = PT<PREC>::ESZ;
   constexpr bool ACCUM = (EPI == EPI_ABS2_MAP || EPI == EPI_ABS2_BEAMS || EPI == EPI_QUAD);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // wave index in a scalar register: the LDS destinations of the direct loads
+  // and the wave's tile offsets are then scalar values
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, kg = lane >> 4;
   int m0, n0, jb0, jb1;

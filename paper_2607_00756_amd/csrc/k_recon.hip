@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_recon_operand(ReconArgs a, void* out, i
   if (rt_lo + 1 < rt_hi) load_slab(rt_lo + 1);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int half = lane >> 5, px32 = lane & 31;
   for (int rt = rt_lo; rt < rt_hi; ++rt) {
     const int r0 = rt * TR;
@@ -243,7 +243,10 @@ __device__ inline void recon_kblk_tile(const ReconArgs& a, void* out, int n_r, i
   constexpr int KB = PREC == BIP_PREC_FP32 ? 16 : 32;  // beams per 64-byte block row
   const int b0 = bt * TB;
   const int W2 = a.W * a.W;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the wave index in a scalar register: the pixel of each step of the pixel
+  // loop below (and its row, column and carrier offsets) is then wave-uniform
+  // scalar work rather than per-lane vector work
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int ts = 0, n_t = 0;
   if (b0 < a.nb) {
     ts = a.tstart[bt];
