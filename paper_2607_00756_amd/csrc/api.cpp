@@ -1108,6 +1108,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       jfocal.push_back(FocalProbeJob{off[4][i], gram ? off[3][i] : off[2][i], H_off[a], W1, W, kd,
                                      (int32_t)kd_of(W1), a, 0});
     }
+    pj.t0 = jprobe.empty() ? 0 : jprobe.back().t0 + (jprobe.back().W * jprobe.back().W + 63) / 64;
     jprobe.push_back(pj);
     det_first[i] = (int64_t)jdet.size();
     if (gram) {
@@ -1177,6 +1178,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     HIPCHK(hipMemcpyAsync(d_jquad, jquad.data(), jquad.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   ProbeArgs pa{};
   pa.win = p->d_win1;
+  pa.n_par = p->Bp1;
   pa.rowptr = p->d_rp1;
   pa.col = p->d_col1;
   pa.w = p->d_w1;
@@ -1210,7 +1212,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     char* PsiT = (char*)ws.take(std::max<int64_t>(pl3, 1) * csz);
     float* PsiC = p->focal ? (float*)ws.take(std::max<int64_t>(pl4, 1) * 8) : nullptr;
     if (ws.used > work_cap) return err(BIP_ENOMEM, "internal: chunk exceeds the workspace");
-    int max_n1 = 0, max_w2 = 0, max_kd = 0, max_m = 0;
+    int max_n1 = 0, max_kd = 0, max_m = 0;
     const int c0 = chunks[c].first, c1 = chunks[c].second, nat = c1 - c0;
     for (int i = c0; i < c1; ++i) {
       const int a = atoms[i];
@@ -1218,7 +1220,6 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       int64_t s[5];
       sizes(a, s);
       max_n1 = std::max<int>(max_n1, (int)n1_of(W));
-      max_w2 = std::max(max_w2, W1 * W1);
       max_kd = std::max<int>(max_kd, (int)kd_of(W1));
       max_m = std::max(max_m, W1);
       if (off[0][i] + s[0] > pl0 || off[1][i] + s[1] > pl1 || off[2][i] + s[2] > pl2 ||
@@ -1253,7 +1254,9 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
     pa.fx = X;
     pa.out = gram ? (void*)PsiT : (void*)X2;
     pa.out_plane = gram ? pl3 : pl2;
-    HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, max_w2, nat, st); }),
+    const int unit0 = jprobe[c0].t0;
+    const int n_units = jprobe[c1 - 1].t0 + (jprobe[c1 - 1].W * jprobe[c1 - 1].W + 63) / 64 - unit0;
+    HIPCHK(timed(p, ST_FOLD, st, [&] { return launch_probe_fold_x(pa, unit0, n_units, nat, st); }),
            "probe fold");
     if (!p->focal) {
       HIPCHK(timed(p, ST_PROBE, st, [&] { return launch_probe_y(pa, precision, !gram, max_kd, nat, st); }),

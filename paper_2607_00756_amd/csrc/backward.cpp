@@ -125,6 +125,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     j.ox = p->ox[a];
     j.kd = (int32_t)roundup((int64_t)p->W[a] * p->W[a], 32);
     j.ldf = (int32_t)roundup((int64_t)p->W[a] * p->W[a], 64);
+    j.t0 = a == 0 ? 0 : jprobe[a - 1].t0 + (jprobe[a - 1].W * jprobe[a - 1].W + 63) / 64;
   }
   // transposed weights (parent -> beams), built once per plan
   if (!p->d_tp1_rp) {
@@ -224,6 +225,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   const float cb = (float)(1.0 / std::sqrt((double)g.ny * g.nx * p->B));
   ProbeArgs pa{};
   pa.win = p->d_win1;
+  pa.n_par = p->Bp1;
   pa.rowptr = p->d_rp1;
   pa.col = p->d_col1;
   pa.w = p->d_w1;
@@ -299,16 +301,17 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
   HIPCHK(hipMemcpyAsync(d_jobs, hj.data(), hj.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   for (int c0 = 0; c0 < na; c0 += nat_max) {
     const int nat = std::min(nat_max, na - c0);
-    int max_w2 = 0, max_n1 = 0, max_kd = 0;
+    int max_n1 = 0, max_kd = 0;
     for (int a = c0; a < c0 + nat; ++a) {
       const int W2 = p->W[a] * p->W[a];
-      max_w2 = std::max(max_w2, W2);
       max_n1 = std::max(max_n1, (int)roundup(W2, 128));
       max_kd = std::max(max_kd, (int)roundup(W2, 32));
     }
     // psi^T [rho][r] (FP32) of every atom of the chunk, exactly as the forward synthesis
     pa.jobs = d_probe + c0;
-    HIPCHK(launch_probe_fold_x(pa, max_w2, nat, st), "probe fold");
+    const ProbeJob& jl = jprobe[c0 + nat - 1];
+    HIPCHK(launch_probe_fold_x(pa, jprobe[c0].t0, jl.t0 + (jl.W * jl.W + 63) / 64 - jprobe[c0].t0, nat, st),
+           "probe fold");
     HIPCHK(launch_probe_y(pa, prec, false, max_kd, nat, st), "probe synthesis");
     for (int a = c0; a < c0 + nat; ++a) {
       const int64_t i = a - c0;

@@ -98,12 +98,13 @@ struct ProbeJob {
   int32_t W, oy, ox; // window
   int32_t kd;        // row pitch of the operand (padded window pixels)
   int32_t ldf;       // row pitch of the DFT workspace
-  int32_t pad;
+  int32_t t0;        // first 64-pixel tile of this job: prefix of ceil(W^2 / 64) over the jobs
 };
 
 struct ProbeArgs {
   const ProbeJob* jobs;
   const float2* win;        // S1 window stack
+  int n_par;                // parents per atom block of the stack
   const int32_t* rowptr;    // CSR of w(1)
   const int32_t* col;
   const float* w;
@@ -118,6 +119,8 @@ struct ProbeArgs {
   int L, ny, nx, mode;
   int Sy, Sx, P, Ppad;
   float cb;                 // probe coefficient c_b
+  int unit0, n_units;       // the launch's pixel tiles (job t0 numbering) and their count
+  int n_jobs;               // jobs of the launch
   float2* fx;               // DFT workspace
   void* out;                // operand planes
   int64_t out_plane;
@@ -358,7 +361,7 @@ hipError_t launch_recon_operand(const ReconArgs& a, void* out, int kind, int pre
 // probe synthesis (k_probe.hip); scan dimensions up to BIP_MAX_SCAN
 constexpr int BIP_MAX_SCAN = 256;
 size_t probe_lds_bytes(int S);
-hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipStream_t s);
+hipError_t launch_probe_fold_x(const ProbeArgs& pa, int unit0, int n_units, int n_jobs, hipStream_t s);
 hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int n_jobs,
                           hipStream_t s);
 

@@ -15,7 +15,8 @@
 // Pass 1, k_probe_fold_x: a workgroup owns 64 window pixels (one per lane) and
 //   one residue row a.  F[c][r] = sum over beams in cell (a, c) of S1~^b(r) is
 //   built in LDS, then X[a][v][r] = sum_c exp(-2 pi i c v / S_x) F[c][r] goes
-//   to the workspace (complex64, r fastest).
+//   to the workspace (complex64, r fastest).  The S_y workgroups of one pixel
+//   tile run on one XCD, so the tile's parent windows are read from its L2.
 // Pass 2, k_probe_y: a workgroup owns 64 window pixels and one scan column v;
 //   psi[u][v][r] = c sum_a exp(-2 pi i a u / S_y) X[a][v][r] is stored as the
 //   contraction operand psi^T[rho][r] (map) or as U_n = H_n psi (detector
@@ -30,6 +31,7 @@ namespace bip {
 namespace {
 
 constexpr int RT = 64;     // window pixels per workgroup (16 per wave)
+constexpr int kBufferWord3 = 0x00020000;  // raw (untyped) buffer descriptor, 32-bit data
 constexpr int NT = 256;    // threads per workgroup (4 wave64)
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -73,19 +75,36 @@ __device__ inline void dft_mfma(const float2* sF, const float2* sT, int S, int o
   }
 }
 
+// 1-D grid.  Workgroups are dispatched to the 8 XCDs in turn, so blocks x,
+// x + 8, x + 16, ... share XCD x: its slot s takes residue row s mod S_y of
+// pixel tile unit0 + 8 (s / S_y) + x, and the S_y rows of a tile run together
+// in one L2.  A tile is 64 pixels of one job (the job with the last t0 <= the
+// tile).  The dispatch order only affects speed.
 __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   extern __shared__ float2 sm[];
   const int Sx = pa.Sx;
   float2* sF = sm;                         // [Sx rounded up to 4][RT]
   float2* sT = sm + ((Sx + 3) & ~3) * RT;  // [Sx]
-  const ProbeJob job = pa.jobs[blockIdx.z];
+  float2* sW = sT + Sx;                    // [L] exp(-2 pi i m / L), gathered per lane
+  const int slot = blockIdx.x >> 3;
+  const int k8 = slot / pa.Sy;
+  const int a = slot - k8 * pa.Sy;
+  const int u = pa.unit0 + 8 * k8 + (blockIdx.x & 7);
+  if (u >= pa.unit0 + pa.n_units) return;  // the grid's last row of 8 tiles
+  int lo = 0, hi = pa.n_jobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pa.jobs[mid].t0 <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  const ProbeJob job = pa.jobs[lo];
   const int W = job.W, W2 = W * W;
-  const int r0 = blockIdx.x * RT;
-  if (r0 >= W2) return;  // uniform: this atom's window is smaller than the grid
+  const int r0 = (u - job.t0) * RT;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int a = blockIdx.y;
   for (int i = threadIdx.x; i < Sx; i += NT) sT[i] = pa.twx[i];
+  for (int i = threadIdx.x; i < pa.L; i += NT) sW[i] = pa.tw[i];
+  __syncthreads();
   const int r = r0 + lane;
   const bool live = r < W2;
   const int rr = live ? r : 0;
@@ -93,6 +112,12 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   const int py = ((job.oy + ry) & (pa.ny - 1)) * (pa.L / pa.ny);
   const int px = ((job.ox + rx) & (pa.nx - 1)) * (pa.L / pa.nx);
   const float2* win = pa.win + job.win_off;
+  // The parent values are read through a buffer descriptor of the atom's
+  // window stack: the parent's offset in a scalar register, the pixel's in a
+  // vector one, so a load needs no per-lane address arithmetic.
+  const __amdgpu_buffer_rsrc_t rwin = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)win, (short)0, pa.n_par * W2 * (int)sizeof(float2), kBufferWord3);
+  const int voff = rr * (int)sizeof(float2);
   for (int c = wave; c < Sx; c += 4) {
     const int cell = a * Sx + c;
     const int k1 = pa.cell_start[cell + 1];
@@ -100,10 +125,16 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
     for (int k = pa.cell_start[cell]; k < k1; ++k) {
       const int b = pa.cell_beams[k];
       const int2 h = pa.beams[b];
-      const float2 t = pa.tw[(h.x * py + h.y * px) & (pa.L - 1)];  // exp(-2 pi i h.r/N)
-      const float2 s = recon_combine(win, W2, rr, pa.ellc + (int64_t)b * ELL_W,
-                                     pa.ellw + (int64_t)b * ELL_W, pa.col, pa.w, pa.mode);
-      F = cadd(F, cmulc(s, t));  // re-tilt by exp(+2 pi i h.r/N)
+      const float2 t = sW[(h.x * py + h.y * px) & (pa.L - 1)];  // exp(-2 pi i h.r/N)
+      const int32_t* ec = pa.ellc + (int64_t)b * ELL_W;
+      const float* ew = pa.ellw + (int64_t)b * ELL_W;
+      float2 D[ELL_K];
+#pragma unroll
+      for (int j = 0; j < ELL_K; ++j)
+        D[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                              rwin, voff, ec[j] * W2 * (int)sizeof(float2), 0));
+      const float2 sv = recon_finish(D, win, W2, rr, ec, ew, pa.col, pa.w, pa.mode);
+      F = cadd(F, cmulc(sv, t));  // re-tilt by exp(+2 pi i h.r/N)
     }
     sF[c * RT + lane] = live ? F : make_float2(0.f, 0.f);
   }
@@ -239,10 +270,17 @@ hipError_t launch_dft_pass(const float2* in, float2* out, int S, int64_t js, int
   return hipGetLastError();
 }
 
-hipError_t launch_probe_fold_x(const ProbeArgs& pa, int max_w2, int n_jobs, hipStream_t s) {
-  if (n_jobs <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((max_w2 + RT - 1) / RT), (unsigned)pa.Sy, (unsigned)n_jobs);
-  return launch_lds(k_probe_fold_x, grid, probe_lds_bytes(pa.Sx), pa, s);
+hipError_t launch_probe_fold_x(const ProbeArgs& pa, int unit0, int n_units, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0 || n_units <= 0) return hipSuccess;
+  if (unit0 < 0 || pa.Sy < 1) return hipErrorInvalidValue;
+  const int64_t blocks = (int64_t)((n_units + 7) / 8) * 8 * pa.Sy;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  ProbeArgs q = pa;
+  q.unit0 = unit0;
+  q.n_units = n_units;
+  q.n_jobs = n_jobs;
+  const size_t lds = probe_lds_bytes(pa.Sx) + (size_t)pa.L * sizeof(float2);
+  return launch_lds(k_probe_fold_x, dim3((unsigned)blocks), lds, q, s);
 }
 
 hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int n_jobs,

@@ -2,8 +2,9 @@
 "Exact PRISM-EELS", Alg. 2 beam subsampling; Alg. 4 subsampled detector and
 crop mask) against the oracle's Alg. 5 with the same f: beam and parent
 counts, then maps (Gram and direct), qEELS and per-beam outputs in FP32 and
-split precision, lattice and hex parents, ragged windows and raster; outputs
-off every atom's crop mask are exactly zero.  Bars: counts exact, outputs
+split precision, lattice and hex parents, ragged windows, rasters that f
+divides and one it does not, with and without focal back-propagation of
+S1; outputs off every atom's crop mask are exactly zero.  Bars: counts exact, outputs
 rel-L2 1e-4."""
 from __future__ import annotations
 
@@ -19,20 +20,21 @@ from tests.gpu_helpers import gpu_run, rel_l2, torch_dev
 pytestmark = pytest.mark.gpu
 
 
-def _case(f, parents, scan):
+def _case(f, parents, scan, focal=False):
     cfg = dataclasses.replace(tiny_cfg(ny=64, nx=64, nz=5, ly=16.0, lx=16.0, alpha=0.03, theta=0.035,
                                        s=2, scan=scan),
-                              parents=parents, n_radial=3, n_angular=6, interp_f=f)
+                              parents=parents, n_radial=3, n_angular=6, interp_f=f, focal=focal)
     tp = tiny_problem(cfg, n_atoms=4, n_ch=2, W=8, seed=83 + f, vscale=25.0, planes=[0, 4, 2, 1],
                       win_sizes=[8, 12, 16, 24])
     return cfg, tp
 
 
-@pytest.mark.parametrize("f,parents,scan", [(2, "lattice", (8, 8)), (4, "lattice", (8, 12)),
-                                            (2, "hex", (6, 10))])
-def test_prism_f_outputs_against_oracle(f, parents, scan):
+@pytest.mark.parametrize("f,parents,scan,focal", [(2, "lattice", (8, 8), False), (4, "lattice", (8, 12), False),
+                                                  (2, "hex", (6, 10), False), (2, "lattice", (7, 9), False),
+                                                  (2, "lattice", (8, 8), True), (4, "hex", (6, 10), True)])
+def test_prism_f_outputs_against_oracle(f, parents, scan, focal):
     from paper_2607_00756_amd import bip
-    cfg, tp = _case(f, parents, scan)
+    cfg, tp = _case(f, parents, scan, focal)
     prob = as_oracle_problem(tp)
     b = E.BiP(prob)
     I_beams = b.run(mode=E.OUT_BEAMS)
@@ -49,7 +51,7 @@ def test_prism_f_outputs_against_oracle(f, parents, scan):
             assert (plan.B, plan.ndet, plan.Bp1, plan.Bp2) == \
                 (len(b.beams), len(b.det), b.part1.n_parents, b.part2.n_parents)
             err = rel_l2(got, want)
-            print(f"[f {f} {parents} scan {scan} mode {mode} prec {prec}] B {plan.B} n_det {plan.ndet} "
+            print(f"[f {f} {parents} scan {scan} focal {focal} mode {mode} prec {prec}] B {plan.B} n_det {plan.ndet} "
                   f"Bp {plan.Bp1}+{plan.Bp2} rel-L2 {err:.2e}")
             assert err < 1e-4
             assert np.all(got.reshape(len(union), -1)[~union] == 0.0)
