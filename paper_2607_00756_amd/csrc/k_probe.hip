@@ -44,22 +44,21 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // lane l holding row l mod 16 and K index l / 16; the B operand is F, lane l
 // holding K index l / 16 and column l mod 16).  Output: lane l holds rows
 // obase + 16 ob + 4 (l / 16) + q, column 16 wave + l mod 16, in xr / xi[ob][q].
-__device__ inline void dft_mfma(const float2* sF, const float2* sT, int S, int obase, int wave,
-                                int lane, v4f (&xr)[4], v4f (&xi)[4]) {
+// The same product restricted to K rows [jb, je) (je - jb a multiple of 4),
+// sF holding row j at j - jb, added to xr / xi.
+__device__ inline void dft_mfma_part(const float2* sF, const float2* sT, int S, int obase, int jb, int je,
+                                     int wave, int lane, v4f (&xr)[4], v4f (&xi)[4]) {
   const int li = lane & 15, lk = lane >> 4;
   int idx[4], step[4];
 #pragma unroll
   for (int ob = 0; ob < 4; ++ob) {
     const int o = obase + 16 * ob + li;
     const int oo = o < S ? o : 0;
-    idx[ob] = (oo * lk) % S;
+    idx[ob] = (oo * (jb + lk)) % S;
     step[ob] = (4 * oo) % S;
-    xr[ob] = v4f{0.f, 0.f, 0.f, 0.f};
-    xi[ob] = v4f{0.f, 0.f, 0.f, 0.f};
   }
-  const int Sc = (S + 3) & ~3;
-  for (int j0 = 0; j0 < Sc; j0 += 4) {
-    const float2 f = sF[(j0 + lk) * RT + 16 * wave + li];
+  for (int j0 = jb; j0 < je; j0 += 4) {
+    const float2 f = sF[(j0 - jb + lk) * RT + 16 * wave + li];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
       if (obase + 16 * ob < S) {  // wave-uniform
@@ -75,17 +74,34 @@ __device__ inline void dft_mfma(const float2* sF, const float2* sT, int S, int o
   }
 }
 
+__device__ inline void dft_mfma(const float2* sF, const float2* sT, int S, int obase, int wave,
+                                int lane, v4f (&xr)[4], v4f (&xi)[4]) {
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    xr[ob] = v4f{0.f, 0.f, 0.f, 0.f};
+    xi[ob] = v4f{0.f, 0.f, 0.f, 0.f};
+  }
+  dft_mfma_part(sF, sT, S, obase, 0, (S + 3) & ~3, wave, lane, xr, xi);
+}
+
+constexpr int FOLD_CH = 64;  // residue cells of the fold held in LDS at a time
+
 // 1-D grid.  Workgroups are dispatched to the 8 XCDs in turn, so blocks x,
 // x + 8, x + 16, ... share XCD x: its slot s takes residue row s mod S_y of
 // pixel tile unit0 + 8 (s / S_y) + x, and the S_y rows of a tile run together
 // in one L2.  A tile is 64 pixels of one job (the job with the last t0 <= the
 // tile).  The dispatch order only affects speed.
+// The residue cells are folded FOLD_CH at a time into LDS, and each chunk's
+// share of the DFT over x is added to the NV = ceil(S_x / 64) output blocks
+// held in registers (the products run in the same K order as one pass).
+template <int NV>
 __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   extern __shared__ float2 sm[];
   const int Sx = pa.Sx;
-  float2* sF = sm;                         // [Sx rounded up to 4][RT]
-  float2* sT = sm + ((Sx + 3) & ~3) * RT;  // [Sx]
-  float2* sW = sT + Sx;                    // [L] exp(-2 pi i m / L), gathered per lane
+  const int CH = min((Sx + 3) & ~3, FOLD_CH);
+  float2* sF = sm;           // [CH][RT]
+  float2* sT = sm + CH * RT; // [Sx]
+  float2* sW = sT + Sx;      // [L] exp(-2 pi i m / L), gathered per lane
   const int slot = blockIdx.x >> 3;
   const int k8 = slot / pa.Sy;
   const int a = slot - k8 * pa.Sy;
@@ -118,41 +134,54 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   const __amdgpu_buffer_rsrc_t rwin = __builtin_amdgcn_make_buffer_rsrc(
       (void*)win, (short)0, pa.n_par * W2 * (int)sizeof(float2), kBufferWord3);
   const int voff = rr * (int)sizeof(float2);
-  for (int c = wave; c < Sx; c += 4) {
-    const int cell = a * Sx + c;
-    const int k1 = pa.cell_start[cell + 1];
-    float2 F = make_float2(0.f, 0.f);
-    for (int k = pa.cell_start[cell]; k < k1; ++k) {
-      const int b = pa.cell_beams[k];
-      const int2 h = pa.beams[b];
-      const float2 t = sW[(h.x * py + h.y * px) & (pa.L - 1)];  // exp(-2 pi i h.r/N)
-      const int32_t* ec = pa.ellc + (int64_t)b * ELL_W;
-      const float* ew = pa.ellw + (int64_t)b * ELL_W;
-      float2 D[ELL_K];
+  v4f xr[NV][4], xi[NV][4];
 #pragma unroll
-      for (int j = 0; j < ELL_K; ++j)
-        D[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
-                                              rwin, voff, ec[j] * W2 * (int)sizeof(float2), 0));
-      const float2 sv = recon_finish(D, win, W2, rr, ec, ew, pa.col, pa.w, pa.mode);
-      F = cadd(F, cmulc(sv, t));  // re-tilt by exp(+2 pi i h.r/N)
+  for (int vi = 0; vi < NV; ++vi)
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      xr[vi][ob] = v4f{0.f, 0.f, 0.f, 0.f};
+      xi[vi][ob] = v4f{0.f, 0.f, 0.f, 0.f};
     }
-    sF[c * RT + lane] = live ? F : make_float2(0.f, 0.f);
+  for (int cc = 0; cc < Sx; cc += CH) {
+    const int ce = min(Sx, cc + CH);
+    const int cp = cc + ((ce - cc + 3) & ~3);  // the chunk's K rows, zero beyond ce
+    for (int c = cc + wave; c < ce; c += 4) {
+      const int cell = a * Sx + c;
+      const int k1 = pa.cell_start[cell + 1];
+      float2 F = make_float2(0.f, 0.f);
+      for (int k = pa.cell_start[cell]; k < k1; ++k) {
+        const int b = pa.cell_beams[k];
+        const int2 h = pa.beams[b];
+        const float2 t = sW[(h.x * py + h.y * px) & (pa.L - 1)];  // exp(-2 pi i h.r/N)
+        const int32_t* ec = pa.ellc + (int64_t)b * ELL_W;
+        const float* ew = pa.ellw + (int64_t)b * ELL_W;
+        float2 D[ELL_K];
+#pragma unroll
+        for (int j = 0; j < ELL_K; ++j)
+          D[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                rwin, voff, ec[j] * W2 * (int)sizeof(float2), 0));
+        const float2 sv = recon_finish(D, win, W2, rr, ec, ew, pa.col, pa.w, pa.mode);
+        F = cadd(F, cmulc(sv, t));  // re-tilt by exp(+2 pi i h.r/N)
+      }
+      sF[(c - cc) * RT + lane] = live ? F : make_float2(0.f, 0.f);
+    }
+    for (int c = ce + wave; c < cp; c += 4) sF[(c - cc) * RT + lane] = make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int vi = 0; vi < NV; ++vi) dft_mfma_part(sF, sT, Sx, 64 * vi, cc, cp, wave, lane, xr[vi], xi[vi]);
+    __syncthreads();  // the chunk is consumed before the next one is folded
   }
-  for (int c = Sx + wave; c < ((Sx + 3) & ~3); c += 4) sF[c * RT + lane] = make_float2(0.f, 0.f);
-  __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
   float2* X = pa.fx + job.fx_off + (int64_t)a * Sx * job.ldf + r0 + 16 * wave + li;
-  for (int v0 = 0; v0 < Sx; v0 += 64) {
-    v4f xr[4], xi[4];
-    dft_mfma(sF, sT, Sx, v0, wave, lane, xr, xi);
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi)
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int v = v0 + 16 * ob + 4 * lk + q;
-        if (v < Sx) X[(int64_t)v * job.ldf] = make_float2(xr[ob][q], xi[ob][q]);
+        const int v = 64 * vi + 16 * ob + 4 * lk + q;
+        if (v < Sx) X[(int64_t)v * job.ldf] = make_float2(xr[vi][ob][q], xi[vi][ob][q]);
       }
-  }
 }
 
 template <int PREC, bool U>
@@ -279,8 +308,14 @@ hipError_t launch_probe_fold_x(const ProbeArgs& pa, int unit0, int n_units, int 
   q.unit0 = unit0;
   q.n_units = n_units;
   q.n_jobs = n_jobs;
-  const size_t lds = probe_lds_bytes(pa.Sx) + (size_t)pa.L * sizeof(float2);
-  return launch_lds(k_probe_fold_x, dim3((unsigned)blocks), lds, q, s);
+  const size_t lds = ((size_t)std::min((pa.Sx + 3) & ~3, FOLD_CH) * RT + pa.Sx + pa.L) * sizeof(float2);
+  switch ((pa.Sx + 63) / 64) {
+    case 1: return launch_lds(k_probe_fold_x<1>, dim3((unsigned)blocks), lds, q, s);
+    case 2: return launch_lds(k_probe_fold_x<2>, dim3((unsigned)blocks), lds, q, s);
+    case 3: return launch_lds(k_probe_fold_x<3>, dim3((unsigned)blocks), lds, q, s);
+    case 4: return launch_lds(k_probe_fold_x<4>, dim3((unsigned)blocks), lds, q, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int n_jobs,
