@@ -184,12 +184,15 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
       }
 }
 
-template <int PREC, bool U>
+// The residue rows a are staged FOLD_CH at a time, each chunk's share of the
+// DFT over y added to the NV = ceil(S_y / 64) output blocks in registers.
+template <int PREC, bool U, int NV>
 __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
   extern __shared__ float2 sm[];
   const int Sy = pa.Sy, Sx = pa.Sx;
-  float2* sG = sm;                         // [Sy rounded up to 4][RT]
-  float2* sT = sm + ((Sy + 3) & ~3) * RT;  // [Sy]
+  const int CH = min((Sy + 3) & ~3, FOLD_CH);
+  float2* sG = sm;            // [CH][RT]
+  float2* sT = sm + CH * RT;  // [Sy]
   const ProbeJob job = pa.jobs[blockIdx.z];
   const int W2 = job.W * job.W;
   const int kd = job.kd;
@@ -202,9 +205,23 @@ __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
   const int r = r0 + lane;
   const bool live = r < W2;
   const float2* X = pa.fx + job.fx_off + (int64_t)v * job.ldf + r;
-  for (int a = wave; a < ((Sy + 3) & ~3); a += 4)
-    sG[a * RT + lane] = (live && a < Sy) ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
-  __syncthreads();
+  v4f xr[NV][4], xi[NV][4];
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi)
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+      xr[vi][ob] = v4f{0.f, 0.f, 0.f, 0.f};
+      xi[vi][ob] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int ac = 0; ac < Sy; ac += CH) {
+    const int ap = ac + ((min(Sy, ac + CH) - ac + 3) & ~3);  // the chunk's K rows, zero from S_y
+    for (int a = ac + wave; a < ap; a += 4)
+      sG[(a - ac) * RT + lane] = (live && a < Sy) ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int vi = 0; vi < NV; ++vi) dft_mfma_part(sG, sT, Sy, 64 * vi, ac, ap, wave, lane, xr[vi], xi[vi]);
+    __syncthreads();  // the chunk is consumed before the next one is staged
+  }
   // this lane's output pixel
   const int li = lane & 15, lk = lane >> 4;
   const int ro = r0 + 16 * wave + li;
@@ -220,18 +237,16 @@ __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
       store_planes<PREC>(pa.out, job.out_off + (int64_t)rho * kd + ro, pa.out_plane, re, im);
     }
   };
-  for (int u0 = 0; u0 < Sy; u0 += 64) {
-    v4f xr[4], xi[4];
-    dft_mfma(sG, sT, Sy, u0, wave, lane, xr, xi);
-    if (in) {
+  if (in) {
+#pragma unroll
+    for (int vi = 0; vi < NV; ++vi)
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int u = u0 + 16 * ob + 4 * lk + q;
-          if (u < Sy) put(u * Sx + v, pa.cb * xr[ob][q], pa.cb * xi[ob][q]);
+          const int u = 64 * vi + 16 * ob + 4 * lk + q;
+          if (u < Sy) put(u * Sx + v, pa.cb * xr[vi][ob][q], pa.cb * xi[vi][ob][q]);
         }
-    }
   }
   // rows P .. Ppad-1 of the operand are zero
   if (blockIdx.y == 0 && in)
@@ -322,16 +337,25 @@ hipError_t launch_probe_y(const ProbeArgs& pa, int prec, bool u, int max_kd, int
                           hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
   const dim3 grid((unsigned)((max_kd + RT - 1) / RT), (unsigned)pa.Sx, (unsigned)n_jobs);
-  const size_t lds = probe_lds_bytes(pa.Sy);
-#define PY(P)                                                              \
-  if (prec == P)                                                           \
-    return u ? launch_lds(k_probe_y<P, true>, grid, lds, pa, s)            \
-             : launch_lds(k_probe_y<P, false>, grid, lds, pa, s);
+  const size_t lds = ((size_t)std::min((pa.Sy + 3) & ~3, FOLD_CH) * RT + pa.Sy) * sizeof(float2);
+  const int nv = (pa.Sy + 63) / 64;
+#define PYV(P, UU, NV) \
+  if (nv == NV) return launch_lds(k_probe_y<P, UU, NV>, grid, lds, pa, s);
+#define PY(P)                                                                                  \
+  if (prec == P) {                                                                             \
+    if (u) {                                                                                   \
+      PYV(P, true, 1) PYV(P, true, 2) PYV(P, true, 3) PYV(P, true, 4)                          \
+    } else {                                                                                   \
+      PYV(P, false, 1) PYV(P, false, 2) PYV(P, false, 3) PYV(P, false, 4)                      \
+    }                                                                                          \
+    return hipErrorInvalidValue;                                                               \
+  }
   PY(BIP_PREC_FP32)
   PY(BIP_PREC_SPLIT_BF16)
   PY(BIP_PREC_BF16)
   PY(BIP_PREC_FP16)
 #undef PY
+#undef PYV
   return hipErrorInvalidValue;
 }
 
