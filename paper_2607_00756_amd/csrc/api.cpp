@@ -1169,6 +1169,16 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
   }
   GemmJob* d_jdet = d_jobs;
   GemmJob* d_jquad = d_jdet + jdet.size();
+  // Gram launches: one per chunk over its atoms' jobs (their slot rows set here)
+  std::vector<int64_t> gram_gx(chunks.size(), 0);
+  if (gram)
+    for (size_t c = 0; c < chunks.size(); ++c) {
+      int tiles = 0;
+      for (int i = chunks[c].first; i < chunks[c].second; ++i)
+        tiles = std::max(tiles, (int)(n1_of(p->W[atoms[i]]) / 128));
+      gram_gx[c] = gemm_gram_plan(&jdet[det_first[chunks[c].first]], chunks[c].second - chunks[c].first, tiles);
+      if (gram_gx[c] > 0x7fffffff) return err(BIP_EUNSUPPORTED, "Gram launch beyond the grid limit");
+    }
   HIPCHK(hipMemcpyAsync(d_probe, jprobe.data(), jprobe.size() * sizeof(ProbeJob), hipMemcpyHostToDevice, st), "jobs");
   if (p->focal && !jfocal.empty())
     HIPCHK(hipMemcpyAsync(d_fjobs, jfocal.data(), jfocal.size() * sizeof(FocalProbeJob), hipMemcpyHostToDevice, st),
@@ -1312,7 +1322,7 @@ static int signal_atoms(bip_plan* p, const std::vector<int32_t>& atoms, int32_t 
       q.gscale = (float)(p->f * p->f) / (gram_scale * gram_scale);
       q.qtri = 1;
       HIPCHK(timed(p, ST_GRAM, st, [&] {
-               return launch_zgemm_gram(gram_prec, precision, q, (int)gemm_gram_blocks(q.tiles, nat), st);
+               return launch_zgemm_gram(gram_prec, precision, q, (int)gram_gx[c], st);
              }),
              "Gram contraction");
       GemmArgs u = g;

@@ -298,6 +298,15 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     sj.W2 = W2;
     sj.ldo = (int32_t)kd;
   }
+  // Gram launches: one per chunk of nat_max atoms (their slot rows set here)
+  std::vector<int64_t> gram_gx;
+  for (int c0 = 0; c0 < na; c0 += nat_max) {
+    const int nat = std::min(nat_max, na - c0);
+    int tiles = 0;
+    for (int a = c0; a < c0 + nat; ++a) tiles = std::max(tiles, (int)(roundup((int64_t)p->W[a] * p->W[a], 128) / 128));
+    gram_gx.push_back(gemm_gram_plan(&hj[c0], nat, tiles));
+    if (gram_gx.back() > 0x7fffffff) return err(BIP_EUNSUPPORTED, "Gram launch beyond the grid limit");
+  }
   HIPCHK(hipMemcpyAsync(d_jobs, hj.data(), hj.size() * sizeof(GemmJob), hipMemcpyHostToDevice, st), "jobs");
   for (int c0 = 0; c0 < na; c0 += nat_max) {
     const int nat = std::min(nat_max, na - c0);
@@ -342,7 +351,7 @@ int bip_eels_backward(bip_plan* p, int32_t n_ch, const float* H, const int64_t* 
     ga.out2 = Gm;
     ga.tiles = max_n1 / 128;
     ga.gscale = 1.f / (gsc * gsc);
-    HIPCHK(launch_zgemm_gram(gprec, prec, ga, (int)gemm_gram_blocks(ga.tiles, nat), st), "Gram");
+    HIPCHK(launch_zgemm_gram(gprec, prec, ga, (int)gram_gx[c0 / nat_max], st), "Gram");
     // R = conj(psi) diag(Ibar) psi^T over the raster
     GemmArgs gr{};
     gr.A = A1;

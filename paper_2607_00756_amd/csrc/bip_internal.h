@@ -50,6 +50,8 @@ struct GemmJob {
                          // B (0: contiguous; K-blocked operands: row count x chunk width)
   int32_t cu0, cnu;      // crop mask of the atom (GemmArgs::crop): raster rows u with
   int32_t cv0, cnv;      // (u - cu0) mod S_y < cnu and columns v with (v - cv0) mod S_x < cnv
+  int32_t s0;            // EPI_GRAMQ: first slot row of the job's tiles (set by gemm_gram_plan)
+  int32_t pad;
 };
 
 // One atom of a batched K-blocked operand reconstruction.
@@ -413,14 +415,17 @@ hipError_t launch_atom_grad_sum(const double* out, const int64_t* first, int n_a
 
 // contraction (k_gemm.hip)
 // grid: (m_tiles, n_tiles, z) for EPI_ABS2_* and EPI_QUAD (z = g.zsplit), (m_tiles,
-// n_tiles, njobs) for EPI_STORE; for EPI_GRAMQ a 1-D grid of gemm_gram_blocks(g.tiles,
-// njobs) workgroups.  epi EPI_STORE + EPI_CONJ_A conjugates the A operand.
+// n_tiles, njobs) for EPI_STORE; for EPI_GRAMQ a 1-D grid of the gemm_gram_plan count
+// for the launch's jobs.  epi EPI_STORE + EPI_CONJ_A conjugates the A operand.
 constexpr int EPI_CONJ_A = 16;
 // EPI_GRAMQ: operands in in_prec, Q stored in out_prec (equal, or FP16 -> SPLIT_BF16)
 hipError_t launch_zgemm_gram(int in_prec, int out_prec, const GemmArgs& g, int gx, hipStream_t s);
 hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, int gz,
                         hipStream_t s);
-int64_t gemm_gram_blocks(int tiles, int njobs);
+// Workgroups of an EPI_GRAMQ launch over the host copies jobs[0 .. njobs) (tiles:
+// the largest job's tiles per side, g.tiles); sets each job's s0.  Call before the
+// jobs are uploaded.
+int64_t gemm_gram_plan(GemmJob* jobs, int njobs, int tiles);
 constexpr int GEMM_MAX_ZSPLIT = 16;
 int gemm_bk(int prec);
 hipError_t launch_reduce_map(const float* partial, int ntiles, int Ppad, int P, float* out,

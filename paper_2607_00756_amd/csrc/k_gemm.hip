@@ -430,7 +430,9 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
     // eight equal contiguous runs of the blocked order, one per XCD: the
     // tiles an XCD runs at once then share a few operand row blocks in its
     // L2, and every XCD holds an equal share of every job, whatever the
-    // window sizes mixed in the launch.
+    // window sizes mixed in the launch.  A job's runs occupy slot rows
+    // s0 .. s0 + ceil(T_j / 8) - 1 (eight workgroups a row), so a launch of
+    // mixed window sizes has no empty workgroups beyond each job's last row.
     const int nt = g.tiles, T = nt * (nt + 1) / 2;
     int ti, tj;
     if (T < 64) {
@@ -445,14 +447,19 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
       }
       tj = ti + tl;
     } else {
-      const int per = (T + 7) / 8;  // slots per XCD and job
-      jb0 = (int)(blockIdx.x / (8 * per));
-      if (jb0 >= g.njobs) return;  // uniform per workgroup
+      const int row = (int)(blockIdx.x >> 3);
+      int lo = 0, hi = g.njobs - 1;  // the job: the last with s0 <= row
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g.jobs[mid].s0 <= row) lo = mid;
+        else hi = mid - 1;
+      }
+      jb0 = lo;
       const int ntj = (g.jobs[jb0].n_lim + BN - 1) / BN, Tj = ntj * (ntj + 1) / 2;
       const int perj = (Tj + 7) / 8;
-      const int l = (int)(blockIdx.x % (8 * per));
-      const int e = (l & 7) * perj + (l >> 3);
-      if ((l >> 3) >= perj || e >= Tj) return;  // uniform per workgroup
+      const int lr = row - g.jobs[jb0].s0;
+      const int e = (int)(blockIdx.x & 7) * perj + lr;
+      if (lr >= perj || e >= Tj) return;  // uniform per workgroup
       blocked_tile(e, ntj, ti, tj);
     }
     jb1 = jb0 + 1;
@@ -743,8 +750,9 @@ hipError_t zgemm_prec(int epi, const GemmArgs& g, dim3 grid, hipStream_t s) {
 
 hipError_t launch_zgemm_gram(int in_prec, int out_prec, const GemmArgs& g, int gx, hipStream_t s) {
   if (gx <= 0 || g.njobs <= 0) return hipSuccess;
-  if (g.tiles <= 0 || gx != gemm_gram_blocks(g.tiles, g.njobs) || !(g.gscale > 0.f))
-    return hipErrorInvalidValue;
+  if (g.tiles <= 0 || !(g.gscale > 0.f)) return hipErrorInvalidValue;
+  const int64_t T = (int64_t)g.tiles * (g.tiles + 1) / 2;
+  if (T < 64 && gx != 8 * (int64_t)((g.njobs + 7) / 8) * T) return hipErrorInvalidValue;
   const dim3 grid(gx, 1, 1);
   if (in_prec == BIP_PREC_FP16 && out_prec == BIP_PREC_SPLIT_BF16)
     return zgemm_launch<BIP_PREC_FP16, EPI_GRAMQ, true, BIP_PREC_SPLIT_BF16>(g, grid, s);
@@ -782,10 +790,16 @@ hipError_t launch_zgemm(int prec, int epi, const GemmArgs& g, int gx, int gy, in
   }
 }
 
-int64_t gemm_gram_blocks(int tiles, int njobs) {
+int64_t gemm_gram_plan(GemmJob* jobs, int njobs, int tiles) {
   const int64_t T = (int64_t)tiles * (tiles + 1) / 2;
   if (T < 64) return 8 * (int64_t)((njobs + 7) / 8) * T;
-  return (int64_t)njobs * 8 * ((T + 7) / 8);
+  int64_t rows = 0;
+  for (int j = 0; j < njobs; ++j) {
+    const int64_t ntj = (jobs[j].n_lim + BN - 1) / BN, Tj = ntj * (ntj + 1) / 2;
+    jobs[j].s0 = (int32_t)rows;
+    rows += (Tj + 7) / 8;
+  }
+  return 8 * rows;
 }
 
 int gemm_bk(int prec) { return prec == BIP_PREC_FP32 ? PT<BIP_PREC_FP32>::BK : 32; }
