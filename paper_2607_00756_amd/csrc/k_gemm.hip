@@ -555,15 +555,29 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
       // coalesced pieces, then every lane reads its elements from there
       constexpr int QR = quad_row<PREC>(), QPL = BM * QR, CH = 16 / ESZ;
       constexpr int NCH = BN / CH;  // 16-byte pieces per row
-      for (int i = tid; i < PT<PREC>::PLANES * BM * NCH; i += NTHREADS) {
-        const int pl = i / (BM * NCH), rem = i - pl * (BM * NCH);
-        const int row = rem / NCH, ch = rem - row * NCH;
-        const int r = n0 + ch * CH;
-        uint4 val = make_uint4(0u, 0u, 0u, 0u);
-        if (r < job.lda)
-          val = *(const uint4*)((const char*)g.A +
-                                (job.a_off + (int64_t)(m0 + row) * job.lda + r + pl * g.a_plane) * ESZ);
-        *(uint4*)(smem + ((int64_t)pl * QPL + row * QR + ch * CH) * ESZ) = val;
+      constexpr int NPC = PT<PREC>::PLANES * BM * NCH;  // pieces of the tile
+      constexpr int QB = 16;  // loads in flight per thread before their LDS stores
+      static_assert(NPC % (NTHREADS * QB) == 0, "whole rounds of pieces");
+      for (int i0 = tid; i0 < NPC; i0 += NTHREADS * QB) {
+        uint4 val[QB];
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+          const int i = i0 + u * NTHREADS;
+          const int pl = i / (BM * NCH), rem = i - pl * (BM * NCH);
+          const int row = rem / NCH, ch = rem - row * NCH;
+          const int r = n0 + ch * CH;
+          val[u] = make_uint4(0u, 0u, 0u, 0u);
+          if (r < job.lda)
+            val[u] = *(const uint4*)((const char*)g.A +
+                                     (job.a_off + (int64_t)(m0 + row) * job.lda + r + pl * g.a_plane) * ESZ);
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+          const int i = i0 + u * NTHREADS;
+          const int pl = i / (BM * NCH), rem = i - pl * (BM * NCH);
+          const int row = rem / NCH, ch = rem - row * NCH;
+          *(uint4*)(smem + ((int64_t)pl * QPL + row * QR + ch * CH) * ESZ) = val[u];
+        }
       }
       __syncthreads();
 #pragma unroll

@@ -215,8 +215,18 @@ __global__ __launch_bounds__(NT) void k_probe_y(const ProbeArgs pa) {
     }
   for (int ac = 0; ac < Sy; ac += CH) {
     const int ap = ac + ((min(Sy, ac + CH) - ac + 3) & ~3);  // the chunk's K rows, zero from S_y
-    for (int a = ac + wave; a < ap; a += 4)
-      sG[(a - ac) * RT + lane] = (live && a < Sy) ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
+    // this wave's rows of the chunk: all loads in flight before the LDS stores
+    float2 xg[FOLD_CH / 4];
+#pragma unroll
+    for (int q = 0; q < FOLD_CH / 4; ++q) {
+      const int a = ac + wave + 4 * q;
+      xg[q] = (a < ap && live && a < Sy) ? X[(int64_t)a * Sx * job.ldf] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < FOLD_CH / 4; ++q) {
+      const int a = ac + wave + 4 * q;
+      if (a < ap) sG[(a - ac) * RT + lane] = xg[q];
+    }
     __syncthreads();
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) dft_mfma_part(sG, sT, Sy, 64 * vi, ac, ap, wave, lane, xr[vi], xi[vi]);
@@ -269,8 +279,21 @@ __global__ __launch_bounds__(NT) void k_dft_pass(const float2* __restrict__ in, 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < S; i += NT) sT[i] = tws[i];
   const int r = r0 + lane;
-  for (int j = wave; j < ((S + 3) & ~3); j += 4)
-    sF[j * RT + lane] = (r < W2 && j < S) ? in[(int64_t)j * js + (int64_t)o * os + r] : make_float2(0.f, 0.f);
+  // this wave's rows, 16 loads in flight before their LDS stores
+  const int Sc = (S + 3) & ~3;
+  for (int j0 = wave; j0 < Sc; j0 += 64) {
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + 4 * q;
+      v[q] = (r < W2 && j < S) ? in[(int64_t)j * js + (int64_t)o * os + r] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + 4 * q;
+      if (j < Sc) sF[j * RT + lane] = v[q];
+    }
+  }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
   const int ro = r0 + 16 * wave + li;
