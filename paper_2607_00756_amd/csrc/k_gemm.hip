@@ -614,6 +614,21 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
       }
     } else {
       // EPI_GRAMQ: element (m, n) = (r, r') of Q = G * sum_c conj(H_c(r)) H_c(r')
+      // H of the tile's 128 rows and 128 columns, every channel, staged in the
+      // (now free) LDS when it fits, so that the per-element channel sums read
+      // LDS instead of waiting on memory once per channel
+      const bool hlds = g.n_ch * 2 * BM * (int)sizeof(float2) <= lds_bytes<PREC, EPI>();
+      float2* sHm = (float2*)smem;
+      float2* sHn = sHm + (hlds ? g.n_ch * BM : 0);
+      if (hlds) {
+        for (int i = tid; i < g.n_ch * BM; i += NTHREADS) {
+          const int c = i / BM, j = i - c * BM;
+          const int64_t hc = job.h_off + (int64_t)c * job.W2;
+          sHm[i] = m0 + j < job.W2 ? g.H[hc + m0 + j] : make_float2(0.f, 0.f);
+          sHn[i] = n0 + j < job.W2 ? g.H[hc + n0 + j] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+      }
 #pragma unroll
       for (int bn = 0; bn < 4; ++bn) {
         const int n = n0 + wn * 64 + bn * 16 + lr;
@@ -627,11 +642,20 @@ __global__ __launch_bounds__(NTHREADS, (occupancy<PREC, EPI>())) void k_zgemm(co
             float qr = 0.f, qi = 0.f;
             if (m < job.W2 && n < job.W2) {
               float hr = 0.f, hi = 0.f;
-              for (int c = 0; c < g.n_ch; ++c) {
-                const float2 a = g.H[job.h_off + (int64_t)c * job.W2 + m];
-                const float2 b = g.H[job.h_off + (int64_t)c * job.W2 + n];
-                hr += a.x * b.x + a.y * b.y;
-                hi += a.x * b.y - a.y * b.x;
+              if (hlds) {
+                for (int c = 0; c < g.n_ch; ++c) {
+                  const float2 a = sHm[c * BM + (m - m0)];
+                  const float2 b = sHn[c * BM + (n - n0)];
+                  hr += a.x * b.x + a.y * b.y;
+                  hi += a.x * b.y - a.y * b.x;
+                }
+              } else {
+                for (int c = 0; c < g.n_ch; ++c) {
+                  const float2 a = g.H[job.h_off + (int64_t)c * job.W2 + m];
+                  const float2 b = g.H[job.h_off + (int64_t)c * job.W2 + n];
+                  hr += a.x * b.x + a.y * b.y;
+                  hi += a.x * b.y - a.y * b.x;
+                }
               }
               qr = cr * hr - ci * hi;
               qi = cr * hi + ci * hr;
