@@ -62,25 +62,39 @@ hipError_t launch_transmit(float2* T, const float* V, int64_t n, float sigma, hi
 }
 
 // Plane-wave columns scale * exp(sign 2 pi i h.r/N); the phase index
-// (h_y y L/N_y + h_x x L/N_x) mod L is exact integer arithmetic.
+// (h_y y L/N_y + h_x x L/N_x) mod L is exact integer arithmetic.  Grid: y =
+// parent column, x = kInitBlocks workgroups striding over the column's
+// element pairs (two adjacent pixels of a row, one 16-byte store).
+constexpr int kInitBlocks = 32;
+
 __global__ void k_init_planewaves(float2* state, const int2* __restrict__ h, int ny, int nx,
                                   const float2* __restrict__ tw, int L, int sign, float scale) {
-  int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y = blockIdx.y;
-  int p = blockIdx.z;
-  if (x >= nx) return;
-  int2 hp = h[p];
-  int m = (hp.x * y * (L / ny) + hp.y * x * (L / nx)) & (L - 1);
-  float2 w = tw[m];                       // exp(-2 pi i m / L)
-  if (sign > 0) w.y = -w.y;
-  state[((size_t)p * ny + y) * nx + x] = cscale(w, scale);
+  const int p = blockIdx.y;
+  const int2 hp = h[p];
+  const int64_t npair = (int64_t)ny * nx / 2;
+  float4* out = (float4*)(state + (int64_t)p * ny * nx);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npair;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(2 * i), y = e / nx, x = e - y * nx;
+    const int my = hp.x * y * (L / ny);
+    float2 w0 = tw[(my + hp.y * x * (L / nx)) & (L - 1)];  // exp(-2 pi i m / L)
+    float2 w1 = tw[(my + hp.y * (x + 1) * (L / nx)) & (L - 1)];
+    if (sign > 0) {
+      w0.y = -w0.y;
+      w1.y = -w1.y;
+    }
+    w0 = cscale(w0, scale);
+    w1 = cscale(w1, scale);
+    out[i] = make_float4(w0.x, w0.y, w1.x, w1.y);
+  }
 }
 
 hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, int nx,
                                   const float2* tw, int L, int sign, float scale, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_planewaves, dim3((nx + 255) / 256, ny, nb), dim3(256), 0, s, state,
-                     h, ny, nx, tw, L, sign, scale);
+  if ((nx & 1) || nb > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_init_planewaves, dim3(kInitBlocks, nb), dim3(256), 0, s, state, h, ny, nx, tw, L,
+                     sign, scale);
   return hipGetLastError();
 }
 
@@ -89,22 +103,35 @@ hipError_t launch_init_planewaves(float2* state, const int2* h, int nb, int ny, 
 // exp(-2 pi i h_y y/ny) at k_x = -h_x (mod nx) and zero at every other k_x.
 __global__ void k_init_planewaves_rowft(float2* state, const int2* __restrict__ h, int ny, int nx,
                                         const float2* __restrict__ tw, int L, float scale) {
-  int x = blockIdx.x * blockDim.x + threadIdx.x;
-  int y = blockIdx.y;
-  int p = blockIdx.z;
-  if (x >= nx) return;
-  int2 hp = h[p];
+  const int p = blockIdx.y;
+  const int2 hp = h[p];
   const int kx = ((-hp.y) % nx + nx) % nx;
-  float2 v = make_float2(0.f, 0.f);
-  if (x == kx) v = cscale(tw[(hp.x * y * (L / ny)) & (L - 1)], scale * (float)nx);
-  state[((size_t)p * ny + y) * nx + x] = v;
+  const int64_t npair = (int64_t)ny * nx / 2;
+  float4* out = (float4*)(state + (int64_t)p * ny * nx);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npair;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(2 * i), y = e / nx, x = e - y * nx;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (x == kx || x + 1 == kx) {
+      const float2 t = cscale(tw[(hp.x * y * (L / ny)) & (L - 1)], scale * (float)nx);
+      if (x == kx) {
+        v.x = t.x;
+        v.y = t.y;
+      } else {
+        v.z = t.x;
+        v.w = t.y;
+      }
+    }
+    out[i] = v;
+  }
 }
 
 hipError_t launch_init_planewaves_rowft(float2* state, const int2* h, int nb, int ny, int nx,
                                         const float2* tw, int L, float scale, hipStream_t s) {
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_planewaves_rowft, dim3((nx + 255) / 256, ny, nb), dim3(256), 0, s, state,
-                     h, ny, nx, tw, L, scale);
+  if ((nx & 1) || nb > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_init_planewaves_rowft, dim3(kInitBlocks, nb), dim3(256), 0, s, state, h, ny, nx,
+                     tw, L, scale);
   return hipGetLastError();
 }
 
