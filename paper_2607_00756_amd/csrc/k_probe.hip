@@ -130,9 +130,12 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
   const float2* win = pa.win + job.win_off;
   // The parent values are read through a buffer descriptor of the atom's
   // window stack: the parent's offset in a scalar register, the pixel's in a
-  // vector one, so a load needs no per-lane address arithmetic.
+  // vector one, so a load needs no per-lane address arithmetic.  A stack
+  // block beyond the descriptor's 32-bit offsets (2 GiB) is read through
+  // 64-bit pointers instead (a choice uniform over the workgroup).
+  const bool rsrc_ok = (int64_t)pa.n_par * W2 * (int64_t)sizeof(float2) <= 0x7fffffff;
   const __amdgpu_buffer_rsrc_t rwin = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)win, (short)0, pa.n_par * W2 * (int)sizeof(float2), kBufferWord3);
+      (void*)win, (short)0, rsrc_ok ? pa.n_par * W2 * (int)sizeof(float2) : 0, kBufferWord3);
   const int voff = rr * (int)sizeof(float2);
   v4f xr[NV][4], xi[NV][4];
 #pragma unroll
@@ -156,10 +159,14 @@ __global__ __launch_bounds__(NT) void k_probe_fold_x(const ProbeArgs pa) {
         const int32_t* ec = pa.ellc + (int64_t)b * ELL_W;
         const float* ew = pa.ellw + (int64_t)b * ELL_W;
         float2 D[ELL_K];
+        if (rsrc_ok) {
 #pragma unroll
-        for (int j = 0; j < ELL_K; ++j)
-          D[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
-                                                rwin, voff, ec[j] * W2 * (int)sizeof(float2), 0));
+          for (int j = 0; j < ELL_K; ++j)
+            D[j] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                  rwin, voff, ec[j] * W2 * (int)sizeof(float2), 0));
+        } else {
+          recon_load(win, W2, rr, ec, D);
+        }
         const float2 sv = recon_finish(D, win, W2, rr, ec, ew, pa.col, pa.w, pa.mode);
         F = cadd(F, cmulc(sv, t));  // re-tilt by exp(+2 pi i h.r/N)
       }
